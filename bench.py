@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the IRK stage solve on one MI355X.
+
+Workload: 2-D heat equation, 5-point finite differences on a 2048 x 2048
+interior grid (4,194,304 unknowns), 7-stage Gauss-Legendre, h_t = 1e-3,
+initial value a sum of 8 seeded random sine modes; each step solves the
+29,360,128-unknown stage system with right-preconditioned flexible GMRES and
+the block preconditioner P_LD (one AMG V-cycle per stage block).  Two forms
+are timed on the same input: FP32 V-cycles/sweeps inside FP64 FGMRES
+("mixed", the headline value) and everything in FP64.
+
+A step is one IRK step (one full stage solve plus the update).  W warm-up
+steps from u0 are discarded; then exactly K steps from u0 are timed with the
+inputs resident in HBM.  The dominant kernel class (largest share of GPU
+time in a profiling pass) is timed with HIP events throughout the timed
+steps, giving its achieved bandwidth against the HBM peak.
+
+The CPU baseline is the oracle (exact sine-transform stepper) on the host,
+and its result also gives the relative L2 error of both GPU paths.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--rtol", type=float, default=1e-9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=1,
+                    help="steps per kernel class in the profiling pre-pass (0 skips it)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_run(S, u0, K, W, torch, profile_class=None):
+    """W warm-up steps from u0 (discarded), then K timed steps from u0."""
+    u = u0.clone()
+    for _ in range(W):
+        u = S.step(u)
+    torch.cuda.synchronize()
+    if profile_class is not None:
+        S.profile_select(profile_class)
+    u = u0.clone()
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        u = S.step(u)
+        iters.append(S.last_stats.iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = S.profile_read() if profile_class is not None else None
+    S.profile_select(None)
+    return u, (t1 - t0), iters, prof
+
+
+def class_shares(S, u0, steps, torch):
+    """GPU milliseconds and algorithmic bytes per kernel class, one class per pass."""
+    from paper_2010_11377_amd.binding import KERNEL_CLASSES
+    out = {}
+    for kc in KERNEL_CLASSES:
+        S.profile_select(kc)
+        u = u0.clone()
+        for _ in range(steps):
+            u = S.step(u)
+        torch.cuda.synchronize()
+        p = S.profile_read()
+        out[kc] = {"ms": p["ms"] / steps, "bytes": p["bytes"] / steps, "launches": p["launches"] / steps}
+    S.profile_select(None)
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2010_11377_amd import problems, tableaux, workloads
+    from paper_2010_11377_amd.solver import IRKSolver
+
+    n, s, h, K, W = args.n, 7, 1e-3, args.steps, args.warmup
+    dev = torch.device("cuda", 0)
+    A, b, c = tableaux.tableau("gauss", s)
+    Kop = problems.heat(n)
+    u0_np = workloads.fourier_modes(n, seed=0)
+    u0 = torch.tensor(u0_np, dtype=torch.float64, device=dev)
+
+    results = {}
+    forms = [("mixed", "mixed")] + ([] if args.no_fp64 else [("fp64", "fp64")])
+    shares = {}
+    for name, prec in forms:
+        t_setup = time.perf_counter()
+        S = IRKSolver(A, b, c, Kop, h, (n, n), precision=prec, rtol=args.rtol, device=dev)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t_setup
+        log("[bench] %s setup %.2fs info %s" % (name, t_setup, S.info()))
+        dom = None
+        if args.profile_steps > 0:
+            shares[name] = class_shares(S, u0, args.profile_steps, torch)
+            dom = max(shares[name], key=lambda k: shares[name][k]["ms"])
+            log("[bench] %s kernel classes (ms/step): %s" % (
+                name, {k: round(v["ms"], 3) for k, v in shares[name].items()}))
+        u, secs, iters, prof = timed_run(S, u0, K, W, torch, dom)
+        log("[bench] %s: %d steps in %.4fs, iters %s" % (name, K, secs, iters))
+        results[name] = {"u": u.cpu().numpy(), "secs": secs, "iters": iters, "prof": prof,
+                         "dominant": dom, "setup_s": t_setup}
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+
+    # CPU baseline: the oracle on the host, same workload
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        from oracle.step import HeatDSTStepper
+        from oracle.tableau import tableau as oracle_tableau
+        cores = len(os.sched_getaffinity(0))
+        Ao, bo, _ = oracle_tableau("gauss", s)
+        t0 = time.perf_counter()
+        st = HeatDSTStepper(Ao, bo, n, h, workers=cores)
+        t_set = time.perf_counter() - t0
+        u = u0_np.copy()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            u = st.step(u)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": K / t_cpu, "unit": "IRK steps/s", "cores": cores, "kind": "oracle",
+               "sample": "the full workload: %d steps of the %dx%d GL7 heat problem by the exact "
+                         "sine-transform stepper (scipy.fft, %d workers); its one-off setup of "
+                         "%.1fs (per-mode 7x7 solves) excluded" % (K, n, n, cores, t_set)}
+        for name in results:
+            ug = results[name]["u"]
+            errs[name] = float(np.linalg.norm(ug - u) / np.linalg.norm(u))
+        log("[bench] oracle %d steps %.2fs (setup %.2fs); rel errors %s" % (K, t_cpu, t_set, errs))
+
+    head = results["mixed"]
+    value = K / head["secs"]
+    prof = head["prof"]
+    roof = None
+    if prof and prof["launches"] > 0 and prof["ms"] > 0:
+        achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "kernel": head["dominant"], "launches": prof["launches"],
+                "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 2),
+                "bytes_per_launch": round(prof["bytes"] / prof["launches"])}
+    line = {
+        "metric": "IRK steps/s to 1e-8 rel, FP64 vs FP32-AMG FGMRES; achieved HBM GB/s",
+        "value": round(value, 3),
+        "unit": "IRK steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(1e3 * head["secs"] / K, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": "heat_2048x2048_gl7_ht1e-3_10steps", "n": n, "s": s, "h_t": h,
+                   "tableau": "gauss_legendre", "preconditioner": "P_LD, AMG V(2,2) red-black GS",
+                   "fgmres_rtol": args.rtol, "u0": "8 random sine modes, seed 0",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "mixed": {"steps_per_s": round(value, 3), "iters_per_step": head["iters"],
+                  "rel_err_vs_oracle": errs.get("mixed"), "setup_s": round(head["setup_s"], 2)},
+    }
+    if "fp64" in results:
+        r = results["fp64"]
+        line["fp64"] = {"steps_per_s": round(K / r["secs"], 3), "ms_per_step": round(1e3 * r["secs"] / K, 3),
+                        "iters_per_step": r["iters"], "rel_err_vs_oracle": errs.get("fp64"),
+                        "setup_s": round(r["setup_s"], 2)}
+        line["speedup_mixed_vs_fp64"] = round(r["secs"] / head["secs"], 3)
+    if "mixed" in shares:
+        tot_b = sum(v["bytes"] for v in shares["mixed"].values())
+        tot_ms = sum(v["ms"] for v in shares["mixed"].values())
+        line["kernel_classes_mixed"] = {k: {"ms_per_step": round(v["ms"], 3),
+                                            "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                                        for k, v in shares["mixed"].items()}
+        line["step_algorithmic_GBps"] = round(tot_b / (head["secs"] / K) / 1e9, 1)
+        line["kernel_time_fraction_of_step"] = round(tot_ms / (1e3 * head["secs"] / K), 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

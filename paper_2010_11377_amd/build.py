@@ -1,0 +1,44 @@
+"""Build libirk.so (HIP, gfx950) in-tree, and the host-only test library.
+
+``python -m paper_2010_11377_amd.build`` or ``build()``.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+
+HIP_SOURCES = ["host_setup.cpp", "kernels.hip", "solver.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", os.path.join(ROOT, "include")]
+
+
+def _run(cmd):
+    proc = subprocess.run(cmd, cwd=CSRC, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in proc.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if proc.returncode != 0:
+        raise RuntimeError("build failed: %s\n%s" % (" ".join(cmd), out))
+    return out
+
+
+def build(verbose=False):
+    """Compile libirk.so (gfx950) and libirk_host_test.so (host C++ only)."""
+    lib = os.path.join(HERE, "libirk.so")
+    tmp = lib + ".tmp"
+    out = _run([HIPCC] + HIP_FLAGS + ["-o", tmp] + HIP_SOURCES)
+    os.replace(tmp, lib)
+    host = os.path.join(HERE, "libirk_host_test.so")
+    out2 = _run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", host + ".tmp",
+                 "host_setup.cpp", "host_test_api.cpp"])
+    os.replace(host + ".tmp", host)
+    if verbose:
+        print(out, out2, sep="\n")
+    return lib
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

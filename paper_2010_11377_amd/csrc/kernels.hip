@@ -1,0 +1,841 @@
+// Device kernels of the IRK stage solver for gfx950 (CDNA4, wave64).
+//
+// Layout: every grid vector is x-fastest (p = j * nx + i); stage vectors are
+// stage-major (element (i, p) at i * N + p); a Krylov column of the stage
+// system is s * N contiguous doubles.
+//
+// The kernels are HBM-bound sparse/vector passes (<= ~1 flop per byte), so
+// they are organised around coalesced loads and few passes over the data:
+//  * the Kronecker SpMM reads every stage vector once and mixes the s values
+//    of K z at a node through the s x s matrix h A held in scalar registers;
+//  * the Gram-Schmidt dot products are fused into the SpMM (the SpMM result
+//    is never written), and the update pass recomputes it instead of reading
+//    it back;
+//  * every reduction is a fixed-order two-stage (block, then single-block)
+//    sum, so results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace irk {
+namespace {
+
+struct Mat8 {
+  double a[64];
+};
+struct Row8 {
+  double c[8];
+};
+
+__device__ __forceinline__ int node_class_d(int i, int j, int nx, int ny) {
+  int cx = (i == 0) ? 0 : (i == nx - 1 ? 2 : 1);
+  int cy = (j == 0) ? 0 : (j == ny - 1 ? 2 : 1);
+  return 3 * cy + cx;
+}
+
+// Sum over the block, valid on thread 0.  Fixed order: wave shuffle tree,
+// then the 4 wave results in order.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) r += red[q];
+  }
+  return r;
+}
+
+// Coefficient k at node p (boundary class q).  A constant-coefficient table
+// has 81 entries and is read through the cache (nearly every lane of a wave
+// reads the same interior entry).
+template <typename T>
+__device__ __forceinline__ T coef(const OpView<T> &op, int q, int k, size_t p, size_t N) {
+  return op.cls ? op.cls[q * 9 + k] : op.arr[(size_t)k * N + p];
+}
+
+// (A x)_p without the diagonal term; also returns the diagonal coefficient.
+template <typename T, typename TX>
+__device__ __forceinline__ T offdiag_apply(const OpView<T> &op, const TX *x, int i,
+                                           int j, size_t p, size_t N, T &diag) {
+  const int nx = op.nx, ny = op.ny;
+  const int q = node_class_d(i, j, nx, ny);
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) continue;
+    if (op.npt == 5 && (k == 0 || k == 2 || k == 6 || k == 8)) continue;
+    const int dx = k % 3 - 1, dy = k / 3 - 1;
+    const int ii = i + dx, jj = j + dy;
+    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+    acc += coef(op, q, k, p, N) * T(x[(size_t)jj * nx + ii]);
+  }
+  diag = coef(op, q, 4, p, N);
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// right-hand sides and norms
+
+__global__ void __launch_bounds__(kBlock)
+    k_rhs_forward(OpView<double> K, const double *__restrict__ u, const double *__restrict__ g,
+                  int s, double *__restrict__ f, double *__restrict__ V0,
+                  double *__restrict__ partial) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double val = 0.0;
+  if (p < N) {
+    const int i = (int)(p % K.nx), j = (int)(p / K.nx);
+    double d;
+    double Ku = offdiag_apply(K, u, i, j, p, N, d);
+    Ku += d * u[p];
+    const double fv = (g ? g[p] : 0.0) - Ku;
+    f[p] = fv;
+    for (int st = 0; st < s; ++st) V0[(size_t)st * N + p] = fv;
+    val = fv * fv * s;
+  }
+  const double r = block_sum(val);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_rhs_copy(const double *__restrict__ rhs, size_t n, double *__restrict__ V0,
+               double *__restrict__ partial) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double val = 0.0;
+  if (e < n) {
+    const double v = rhs[e];
+    V0[e] = v;
+    val = v * v;
+  }
+  const double r = block_sum(val);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_finalize_norm(const double *__restrict__ partial, int nblk, double *__restrict__ scale,
+                    int col, double *__restrict__ norm_out) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial[b];
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(r);
+    scale[col] = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+    if (norm_out) *norm_out = nrm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block substitution coupling (Sec. 4.2)
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_couple(OpView<T> K, const double *__restrict__ v, const double *__restrict__ scale_j,
+             const T *__restrict__ z, Row8 crow, int s, int i, T *__restrict__ b) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  const int ii = (int)(p % K.nx), jj = (int)(p / K.nx);
+  const double sc = *scale_j;
+  T acc = T(sc * v[(size_t)i * N + p]);
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < kMaxStages; ++k)
+    if (k < s && crow.c[k] != 0.0) any = true;
+  if (any) {
+    const int q = node_class_d(ii, jj, K.nx, K.ny);
+    T kc = T(0);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      if (K.npt == 5 && (t == 0 || t == 2 || t == 6 || t == 8)) continue;
+      const int dx = t % 3 - 1, dy = t / 3 - 1;
+      const int xi = ii + dx, yj = jj + dy;
+      if (xi < 0 || xi >= K.nx || yj < 0 || yj >= K.ny) continue;
+      const size_t pn = (size_t)yj * K.nx + xi;
+      T comb = T(0);
+#pragma unroll
+      for (int k = 0; k < kMaxStages; ++k)
+        if (k < s && crow.c[k] != 0.0) comb += T(crow.c[k]) * z[(size_t)k * N + pn];
+      kc += coef(K, q, t, p, N) * comb;
+    }
+    acc -= kc;
+  }
+  b[p] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle pieces
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_rb_sweep(OpView<T> D, T *__restrict__ x, const T *__restrict__ b, int color, int ncolors,
+               int zero_init) {
+  const size_t N = (size_t)D.nx * D.ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  const int i = (int)(p % D.nx), j = (int)(p / D.nx);
+  const int c = (ncolors == 2) ? ((i + j) & 1) : ((i & 1) + 2 * (j & 1));
+  if (c != color) {
+    if (zero_init) x[p] = T(0);
+    return;
+  }
+  T d;
+  T off = T(0);
+  if (zero_init) {
+    d = coef(D, node_class_d(i, j, D.nx, D.ny), 4, p, N);
+  } else {
+    off = offdiag_apply(D, x, i, j, p, N, d);
+  }
+  x[p] = (b[p] - off) / d;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_resid_restrict(OpView<T> D, const T *__restrict__ x, const T *__restrict__ b,
+                     T *__restrict__ rc) {
+  const int ncx = D.nx / 2, ncy = D.ny / 2;
+  const size_t Nc = (size_t)ncx * ncy;
+  const size_t N = (size_t)D.nx * D.ny;
+  const size_t I = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (I >= Nc) return;
+  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
+  T acc = T(0);
+#pragma unroll
+  for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = 2 * Ix + a, j = 2 * Iy + bb;
+      const size_t p = (size_t)j * D.nx + i;
+      T d;
+      const T off = offdiag_apply(D, x, i, j, p, N, d);
+      acc += b[p] - off - d * x[p];
+    }
+  rc[I] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_prolong_add(int nx, int ny, const T *__restrict__ ec, T *__restrict__ x) {
+  const size_t N = (size_t)nx * ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  const int fx = (int)(p % nx), fy = (int)(p / nx);
+  const int ncx = nx / 2, ncy = ny / 2;
+  const int Ix = fx / 2, Iy = fy / 2;
+  const int nbx = (fx & 1) ? Ix + 1 : Ix - 1;
+  const int nby = (fy & 1) ? Iy + 1 : Iy - 1;
+  const bool hx = nbx >= 0 && nbx < ncx, hy = nby >= 0 && nby < ncy;
+  T v = T(0.5625) * ec[(size_t)Iy * ncx + Ix];
+  if (hx) v += T(0.1875) * ec[(size_t)Iy * ncx + nbx];
+  if (hy) v += T(0.1875) * ec[(size_t)nby * ncx + Ix];
+  if (hx && hy) v += T(0.0625) * ec[(size_t)nby * ncx + nbx];
+  x[p] += v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_dense_solve(const T *__restrict__ Cinv, int n, const T *__restrict__ b, T *__restrict__ x) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n) return;
+  const T *row = Cinv + (size_t)r * n;
+  T acc = T(0);
+  for (int c = 0; c < n; ++c) acc += row[c] * b[c];
+  x[r] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Kronecker SpMM with fused Gram-Schmidt
+
+// w_i(p) = z_i(p) + sum_k hA[i][k] (K z_k)(p) for all s stages at node p.
+template <typename TZ, int S>
+__device__ __forceinline__ void kron_apply(const OpView<double> &K, 
+                                           const TZ *__restrict__ z, const Mat8 &hA, size_t p,
+                                           size_t N, double *w) {
+  const int i = (int)(p % K.nx), j = (int)(p / K.nx);
+  const int q = node_class_d(i, j, K.nx, K.ny);
+  double kz[S];
+#pragma unroll
+  for (int st = 0; st < S; ++st) kz[st] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    if (K.npt == 5 && (t == 0 || t == 2 || t == 6 || t == 8)) continue;
+    const int dx = t % 3 - 1, dy = t / 3 - 1;
+    const int xi = i + dx, yj = j + dy;
+    if (xi < 0 || xi >= K.nx || yj < 0 || yj >= K.ny) continue;
+    const size_t pn = (size_t)yj * K.nx + xi;
+    const double a = coef(K, q, t, p, N);
+#pragma unroll
+    for (int st = 0; st < S; ++st) kz[st] += a * double(z[(size_t)st * N + pn]);
+  }
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    double acc = double(z[(size_t)r * N + p]);
+#pragma unroll
+    for (int st = 0; st < S; ++st) acc += hA.a[r * 8 + st] * kz[st];
+    w[r] = acc;
+  }
+}
+
+template <typename TZ, int S>
+__global__ void __launch_bounds__(kBlock)
+    k_spmm_dots(OpView<double> K, const TZ *__restrict__ z, Mat8 hA, const double *__restrict__ V,
+                const double *__restrict__ scale, const KrylovState *__restrict__ ks,
+                double *__restrict__ partial) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t sN = (size_t)S * N;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const int nblk = gridDim.x;
+  const int jj = ks->j;
+  double w[S];
+  const bool live = p < N;
+  if (live) kron_apply<TZ, S>(K, z + (size_t)jj * sN, hA, p, N, w);
+  for (int m = 0; m <= jj; ++m) {
+    double acc = 0.0;
+    if (live) {
+      const double *Vm = V + (size_t)m * sN;
+#pragma unroll
+      for (int r = 0; r < S; ++r) acc += Vm[(size_t)r * N + p] * w[r];
+      acc *= scale[m];
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[(size_t)m * nblk + blockIdx.x] = t;
+  }
+}
+
+template <typename TZ, int S>
+__global__ void __launch_bounds__(kBlock)
+    k_spmm_update(OpView<double> K, const TZ *__restrict__ z, Mat8 hA,
+                  const double *__restrict__ V, const double *__restrict__ scale,
+                  const double *__restrict__ hcol, const KrylovState *__restrict__ ks,
+                  double *__restrict__ Vall, double *__restrict__ partial) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t sN = (size_t)S * N;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const int jj = ks->j;
+  double val = 0.0;
+  if (p < N) {
+    double w[S];
+    kron_apply<TZ, S>(K, z + (size_t)jj * sN, hA, p, N, w);
+    for (int m = 0; m <= jj; ++m) {
+      const double c = hcol[m] * scale[m];
+      const double *Vm = V + (size_t)m * sN;
+#pragma unroll
+      for (int r = 0; r < S; ++r) w[r] -= c * Vm[(size_t)r * N + p];
+    }
+    double *vout = Vall + (size_t)(jj + 1) * sN;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      vout[(size_t)r * N + p] = w[r];
+      val += w[r] * w[r];
+    }
+  }
+  const double t = block_sum(val);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// Second Gram-Schmidt pass on the new column V_{j+1} (elements EPT per thread).
+constexpr int kEPT = 4;
+
+__global__ void __launch_bounds__(kBlock)
+    k_vec_dots(const double *__restrict__ V, size_t n, const double *__restrict__ scale,
+               const KrylovState *__restrict__ ks, double *__restrict__ partial) {
+  const int jj = ks->j;
+  const double *vin = V + (size_t)(jj + 1) * n;
+  const size_t e0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * kEPT;
+  double x[kEPT];
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) x[q] = (e0 + q < n) ? vin[e0 + q] : 0.0;
+  const int nblk = gridDim.x;
+  for (int m = 0; m <= jj; ++m) {
+    const double *Vm = V + (size_t)m * n;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kEPT; ++q)
+      if (e0 + q < n) acc += x[q] * Vm[e0 + q];
+    acc *= scale[m];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[(size_t)m * nblk + blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_vec_update(double *__restrict__ V, size_t n, const double *__restrict__ scale,
+                 const double *__restrict__ h2, const KrylovState *__restrict__ ks,
+                 double *__restrict__ partial) {
+  const int jj = ks->j;
+  double *vin = V + (size_t)(jj + 1) * n;
+  const size_t e0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * kEPT;
+  double x[kEPT];
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) x[q] = (e0 + q < n) ? vin[e0 + q] : 0.0;
+  for (int m = 0; m <= jj; ++m) {
+    const double c = h2[m] * scale[m];
+    const double *Vm = V + (size_t)m * n;
+#pragma unroll
+    for (int q = 0; q < kEPT; ++q)
+      if (e0 + q < n) x[q] -= c * Vm[e0 + q];
+  }
+  double val = 0.0;
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q)
+    if (e0 + q < n) {
+      vin[e0 + q] = x[q];
+      val += x[q] * x[q];
+    }
+  const double t = block_sum(val);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_reduce_cols(const double *__restrict__ partial, int nblk,
+                  const KrylovState *__restrict__ ks, double *__restrict__ out) {
+  const int m = blockIdx.x;
+  if (m > ks->j) return;  // uniform per block
+  double acc = 0.0;
+  const double *col = partial + (size_t)m * nblk;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += col[b];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) out[m] = t;
+}
+
+// Hessenberg column j: H[:, j] = h1 (+ h2), H[j+1, j] = ||v_{j+1}||, rotate
+// with the stored Givens rotations, form the new one, update g and the
+// residual estimate |g_{j+1}|, set the lazy scale of V_{j+1}, advance j.
+__global__ void __launch_bounds__(kBlock)
+    k_givens(const double *__restrict__ h1, const double *__restrict__ h2,
+             const double *__restrict__ partial_norm, int nblk, double *__restrict__ H, int ldh,
+             double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
+             double *__restrict__ scale, KrylovState *__restrict__ ks, double beta, double rtol,
+             double *__restrict__ host_resid) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial_norm[b];
+  const double nrm2 = block_sum(acc);
+  if (threadIdx.x != 0) return;
+  const int j = ks->j;
+  double *Hc = H + (size_t)j * ldh;
+  for (int m = 0; m <= j; ++m) Hc[m] = h1[m] + (h2 ? h2[m] : 0.0);
+  const double nrm = sqrt(nrm2);
+  Hc[j + 1] = nrm;
+  for (int m = 0; m < j; ++m) {
+    const double a = Hc[m], bb = Hc[m + 1];
+    Hc[m] = cs[m] * a + sn[m] * bb;
+    Hc[m + 1] = -sn[m] * a + cs[m] * bb;
+  }
+  const double a = Hc[j], bb = Hc[j + 1];
+  const double r = hypot(a, bb);
+  double c = 1.0, sv = 0.0;
+  if (r > 0.0) {
+    c = a / r;
+    sv = bb / r;
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  Hc[j] = r;
+  Hc[j + 1] = 0.0;
+  g[j + 1] = -sv * g[j];
+  g[j] = c * g[j];
+  const double res = fabs(g[j + 1]);
+  scale[j + 1] = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+  const bool bad = !isfinite(nrm) || !isfinite(res) || !(r > 0.0);
+  ks->breakdown = bad ? 1 : (nrm == 0.0 ? 2 : 0);
+  ks->converged = (res <= rtol * beta) ? 1 : 0;
+  ks->j = j + 1;
+  host_resid[0] = res;
+  host_resid[1] = (double)ks->breakdown;
+}
+
+__global__ void k_solve_upper(const double *__restrict__ H, int ldh, const double *__restrict__ g,
+                              int k, double *__restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int r = k - 1; r >= 0; --r) {
+    double acc = g[r];
+    for (int c = r + 1; c < k; ++c) acc -= H[(size_t)c * ldh + r] * y[c];
+    y[r] = acc / H[(size_t)r * ldh + r];
+  }
+}
+
+template <typename TZ>
+__global__ void __launch_bounds__(kBlock)
+    k_accumulate(const TZ *__restrict__ Z, size_t zs, const double *__restrict__ y, int k,
+                 size_t n, double *__restrict__ acc) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  double a = acc[e];
+  for (int j = 0; j < k; ++j) a += y[j] * double(Z[(size_t)j * zs + e]);
+  acc[e] = a;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_combine(const double *__restrict__ u_in, const double *__restrict__ x, Row8 wts, int s,
+              size_t N, double *__restrict__ u_out) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  double a = u_in[p];
+#pragma unroll
+  for (int i = 0; i < kMaxStages; ++i)
+    if (i < s) a += wts.c[i] * x[(size_t)i * N + p];
+  u_out[p] = a;
+}
+
+template <int S>
+__global__ void __launch_bounds__(kBlock)
+    k_residual_full(OpView<double> K, const double *__restrict__ x, Mat8 hA,
+                    const double *__restrict__ rhs, const double *__restrict__ f,
+                    double *__restrict__ V0, double *__restrict__ partial) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double val = 0.0;
+  if (p < N) {
+    double w[S];
+    kron_apply<double, S>(K, x, hA, p, N, w);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      const double b = rhs ? rhs[(size_t)r * N + p] : f[p];
+      const double res = b - w[r];
+      V0[(size_t)r * N + p] = res;
+      val += res * res;
+    }
+  }
+  const double t = block_sum(val);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+template <int S>
+__global__ void __launch_bounds__(kBlock)
+    k_kron_out(OpView<double> K, const double *__restrict__ x, Mat8 hA, double *__restrict__ y) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  double w[S];
+  kron_apply<double, S>(K, x, hA, p, N, w);
+#pragma unroll
+  for (int r = 0; r < S; ++r) y[(size_t)r * N + p] = w[r];
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_stage_values(const double *__restrict__ u, const double *__restrict__ k, Mat8 hA, int s,
+                   size_t N, double *__restrict__ U) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  double kv[kMaxStages];
+#pragma unroll
+  for (int i = 0; i < kMaxStages; ++i) kv[i] = (i < s) ? k[(size_t)i * N + p] : 0.0;
+  const double up = u[p];
+#pragma unroll
+  for (int i = 0; i < kMaxStages; ++i) {
+    if (i >= s) break;
+    double a = up;
+#pragma unroll
+    for (int jx = 0; jx < kMaxStages; ++jx)
+      if (jx < s) a += hA.a[i * 8 + jx] * kv[jx];
+    U[(size_t)i * N + p] = a;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_adjoint_lambda(OpView<double> K, const double *__restrict__ lam_in,
+                     const double *__restrict__ psi, int s, double *__restrict__ lam_out) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  const int i = (int)(p % K.nx), j = (int)(p / K.nx);
+  const int q = node_class_d(i, j, K.nx, K.ny);
+  double acc = 0.0;
+  for (int t = 0; t < 9; ++t) {
+    if (K.npt == 5 && (t == 0 || t == 2 || t == 6 || t == 8)) continue;
+    const int xi = i + t % 3 - 1, yj = j + t / 3 - 1;
+    if (xi < 0 || xi >= K.nx || yj < 0 || yj >= K.ny) continue;
+    const size_t pn = (size_t)yj * K.nx + xi;
+    double sp = 0.0;
+    for (int st = 0; st < s; ++st) sp += psi[(size_t)st * N + pn];
+    acc += coef(K, q, t, p, N) * sp;
+  }
+  lam_out[p] = lam_in[p] - acc;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_scaled_broadcast(const double *__restrict__ lam, Row8 wts, int s, size_t N,
+                       double *__restrict__ rhs) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= N) return;
+  const double l = lam[p];
+  for (int i = 0; i < s; ++i) rhs[(size_t)i * N + p] = wts.c[i] * l;
+}
+
+// value of a stage vector at full-grid node (I, J); zero on the boundary.
+__device__ __forceinline__ double full_val(const double *v, int I, int J, int nx, int ny) {
+  if (I < 1 || I > nx || J < 1 || J > ny) return 0.0;
+  return v[(size_t)(J - 1) * nx + (I - 1)];
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_grad_nodes(const double *__restrict__ psi, const double *__restrict__ U, int s, int nx,
+                 int ny, double inv_h2, double *__restrict__ gnode) {
+  const int NX = nx + 2, NY = ny + 2;
+  const size_t P = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (P >= (size_t)NX * NY) return;
+  const int I = (int)(P % NX), J = (int)(P / NX);
+  const size_t N = (size_t)nx * ny;
+  double acc = 0.0;
+  // faces: east (I,J)-(I+1,J), west (I-1,J)-(I,J) on rows 1..ny;
+  //        north (I,J)-(I,J+1), south (I,J-1)-(I,J) on columns 1..nx.
+  const int nb[4][2] = {{I + 1, J}, {I - 1, J}, {I, J + 1}, {I, J - 1}};
+  for (int f = 0; f < 4; ++f) {
+    const int QI = nb[f][0], QJ = nb[f][1];
+    const bool horizontal = f < 2;
+    if (horizontal) {
+      if (J < 1 || J > ny || QI < 0 || QI > nx + 1) continue;
+    } else {
+      if (I < 1 || I > nx || QJ < 0 || QJ > ny + 1) continue;
+    }
+    double face = 0.0;
+    for (int st = 0; st < s; ++st) {
+      const double *ps = psi + (size_t)st * N;
+      const double *us = U + (size_t)st * N;
+      face += (full_val(ps, I, J, nx, ny) - full_val(ps, QI, QJ, nx, ny)) *
+              (full_val(us, I, J, nx, ny) - full_val(us, QI, QJ, nx, ny));
+    }
+    acc += face;
+  }
+  gnode[P] += -0.5 * inv_h2 * acc;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_nonfinite(const double *__restrict__ x, size_t n, double *__restrict__ partial) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double bad = 0.0;
+  if (e < n && !isfinite(x[e])) bad = 1.0;
+  const double t = block_sum(bad);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+inline unsigned nblocks(size_t n, size_t per = kBlock) { return (unsigned)((n + per - 1) / per); }
+
+Mat8 pack_mat(const double *hA, int s) {
+  Mat8 m{};
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) m.a[i * 8 + j] = hA[i * s + j];
+  return m;
+}
+
+Row8 pack_row(const double *c, int s) {
+  Row8 r{};
+  for (int i = 0; i < s; ++i) r.c[i] = c[i];
+  return r;
+}
+
+}  // namespace
+
+namespace kern {
+
+void rhs_forward(const OpView<double> &K, const double *u, const double *g, int s, double *f,
+                 double *V0, double *partial, hipStream_t st) {
+  const size_t N = (size_t)K.nx * K.ny;
+  k_rhs_forward<<<nblocks(N), kBlock, 0, st>>>(K, u, g, s, f, V0, partial);
+}
+
+void rhs_copy(const double *rhs, size_t n, double *V0, double *partial, hipStream_t st) {
+  k_rhs_copy<<<nblocks(n), kBlock, 0, st>>>(rhs, n, V0, partial);
+}
+
+void finalize_norm(const double *partial, int nblk, double *scale, int col, double *norm_out,
+                   hipStream_t st) {
+  k_finalize_norm<<<1, kBlock, 0, st>>>(partial, nblk, scale, col, norm_out);
+}
+
+template <typename T>
+void couple(const OpView<T> &K, const double *v, const double *scale_j, const T *z,
+            const double *C, int s, int i, T *b, hipStream_t st) {
+  const size_t N = (size_t)K.nx * K.ny;
+  k_couple<T><<<nblocks(N), kBlock, 0, st>>>(K, v, scale_j, z, pack_row(C, s), s, i, b);
+}
+
+template <typename T>
+void rb_sweep(const OpView<T> &D, T *x, const T *b, int color, int zero_init, hipStream_t st) {
+  const size_t N = (size_t)D.nx * D.ny;
+  const int ncolors = (D.npt == 5) ? 2 : 4;
+  k_rb_sweep<T><<<nblocks(N), kBlock, 0, st>>>(D, x, b, color, ncolors, zero_init);
+}
+
+template <typename T>
+void resid_restrict(const OpView<T> &D, const T *x, const T *b, T *rc, hipStream_t st) {
+  const size_t Nc = (size_t)(D.nx / 2) * (D.ny / 2);
+  k_resid_restrict<T><<<nblocks(Nc), kBlock, 0, st>>>(D, x, b, rc);
+}
+
+template <typename T>
+void prolong_add(int nx, int ny, const T *ec, T *x, hipStream_t st) {
+  k_prolong_add<T><<<nblocks((size_t)nx * ny), kBlock, 0, st>>>(nx, ny, ec, x);
+}
+
+template <typename T>
+void dense_solve(const T *Cinv, int n, const T *b, T *x, hipStream_t st) {
+  k_dense_solve<T><<<nblocks(n), kBlock, 0, st>>>(Cinv, n, b, x);
+}
+
+#define IRK_DISPATCH_S(s, KERNEL, ...)                     \
+  switch (s) {                                             \
+    case 1: KERNEL(1, __VA_ARGS__); break;                 \
+    case 2: KERNEL(2, __VA_ARGS__); break;                 \
+    case 3: KERNEL(3, __VA_ARGS__); break;                 \
+    case 4: KERNEL(4, __VA_ARGS__); break;                 \
+    case 5: KERNEL(5, __VA_ARGS__); break;                 \
+    case 6: KERNEL(6, __VA_ARGS__); break;                 \
+    case 7: KERNEL(7, __VA_ARGS__); break;                 \
+    default: KERNEL(8, __VA_ARGS__); break;                \
+  }
+
+template <typename TZ>
+void spmm_dots(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
+               const double *scale, const KrylovState *ks, int jmax, double *partial,
+               hipStream_t st) {
+  (void)jmax;
+  const size_t N = (size_t)K.nx * K.ny;
+  const Mat8 m = pack_mat(hA, s);
+#define L_SPMM_DOTS(S_, dummy) \
+  k_spmm_dots<TZ, S_><<<nblocks(N), kBlock, 0, st>>>(K, z, m, V, scale, ks, partial)
+  IRK_DISPATCH_S(s, L_SPMM_DOTS, 0)
+#undef L_SPMM_DOTS
+}
+
+template <typename TZ>
+void spmm_update(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
+                 const double *scale, const double *hcol, const KrylovState *ks, double *vout,
+                 double *partial, hipStream_t st) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const Mat8 m = pack_mat(hA, s);
+#define L_SPMM_UPD(S_, dummy) \
+  k_spmm_update<TZ, S_><<<nblocks(N), kBlock, 0, st>>>(K, z, m, V, scale, hcol, ks, vout, partial)
+  IRK_DISPATCH_S(s, L_SPMM_UPD, 0)
+#undef L_SPMM_UPD
+}
+
+void vec_dots(const double *vin, size_t n, const double *V, const double *scale,
+              const KrylovState *ks, int jmax, double *partial, hipStream_t st) {
+  (void)vin;
+  (void)jmax;
+  k_vec_dots<<<nblocks(n, (size_t)kBlock * kEPT), kBlock, 0, st>>>(V, n, scale, ks, partial);
+}
+
+void vec_update(double *vin, size_t n, const double *V, const double *scale, const double *h2,
+                const KrylovState *ks, double *partial, hipStream_t st) {
+  (void)vin;
+  k_vec_update<<<nblocks(n, (size_t)kBlock * kEPT), kBlock, 0, st>>>(const_cast<double *>(V), n,
+                                                                     scale, h2, ks, partial);
+}
+
+void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, double *out,
+                 hipStream_t st) {
+  k_reduce_cols<<<jmax + 1, kBlock, 0, st>>>(partial, nblk, ks, out);
+}
+
+void givens(const double *h1, const double *h2, const double *partial_norm, int nblk, double *H,
+            int ldh, double *cs, double *sn, double *g, double *scale, KrylovState *ks,
+            double beta, double rtol, double *host_resid, hipStream_t st) {
+  k_givens<<<1, kBlock, 0, st>>>(h1, h2, partial_norm, nblk, H, ldh, cs, sn, g, scale, ks, beta,
+                                 rtol, host_resid);
+}
+
+void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st) {
+  k_solve_upper<<<1, 64, 0, st>>>(H, ldh, g, k, y);
+}
+
+template <typename TZ>
+void accumulate_solution(const TZ *Z, size_t zs, const double *y, int k, size_t n, double *acc,
+                         hipStream_t st) {
+  k_accumulate<TZ><<<nblocks(n), kBlock, 0, st>>>(Z, zs, y, k, n, acc);
+}
+
+void combine_stages(const double *u_in, const double *x, const double *wts, int s, size_t N,
+                    double *u_out, hipStream_t st) {
+  k_combine<<<nblocks(N), kBlock, 0, st>>>(u_in, x, pack_row(wts, s), s, N, u_out);
+}
+
+void residual_full(const OpView<double> &K, const double *x, const double *hA, int s,
+                   const double *rhs, const double *f, double *V0, double *partial,
+                   hipStream_t st) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const Mat8 m = pack_mat(hA, s);
+#define L_RES(S_, dummy) \
+  k_residual_full<S_><<<nblocks(N), kBlock, 0, st>>>(K, x, m, rhs, f, V0, partial)
+  IRK_DISPATCH_S(s, L_RES, 0)
+#undef L_RES
+}
+
+void kron_apply(const OpView<double> &K, const double *x, const double *hA, int s, double *y,
+                hipStream_t st) {
+  const size_t N = (size_t)K.nx * K.ny;
+  const Mat8 m = pack_mat(hA, s);
+#define L_KRON(S_, dummy) k_kron_out<S_><<<nblocks(N), kBlock, 0, st>>>(K, x, m, y)
+  IRK_DISPATCH_S(s, L_KRON, 0)
+#undef L_KRON
+}
+
+void stage_values(const double *u, const double *k, const double *hA, int s, size_t N, double *U,
+                  hipStream_t st) {
+  k_stage_values<<<nblocks(N), kBlock, 0, st>>>(u, k, pack_mat(hA, s), s, N, U);
+}
+
+void adjoint_lambda(const OpView<double> &K, const double *lam_in, const double *psi, int s,
+                    double *lam_out, hipStream_t st) {
+  const size_t N = (size_t)K.nx * K.ny;
+  k_adjoint_lambda<<<nblocks(N), kBlock, 0, st>>>(K, lam_in, psi, s, lam_out);
+}
+
+void scaled_broadcast(const double *lam, const double *wts, int s, size_t N, double *rhs,
+                      hipStream_t st) {
+  k_scaled_broadcast<<<nblocks(N), kBlock, 0, st>>>(lam, pack_row(wts, s), s, N, rhs);
+}
+
+void grad_nodes(const double *psi, const double *U, int s, int nx, int ny, double inv_h2,
+                double *gnode, hipStream_t st) {
+  k_grad_nodes<<<nblocks((size_t)(nx + 2) * (ny + 2)), kBlock, 0, st>>>(psi, U, s, nx, ny, inv_h2,
+                                                                         gnode);
+}
+
+void nonfinite_check(const double *x, size_t n, double *partial, hipStream_t st) {
+  k_nonfinite<<<nblocks(n), kBlock, 0, st>>>(x, n, partial);
+}
+
+// explicit instantiations
+template void couple<float>(const OpView<float> &, const double *, const double *, const float *,
+                            const double *, int, int, float *, hipStream_t);
+template void couple<double>(const OpView<double> &, const double *, const double *,
+                             const double *, const double *, int, int, double *, hipStream_t);
+template void rb_sweep<float>(const OpView<float> &, float *, const float *, int, int, hipStream_t);
+template void rb_sweep<double>(const OpView<double> &, double *, const double *, int, int,
+                               hipStream_t);
+template void resid_restrict<float>(const OpView<float> &, const float *, const float *, float *,
+                                    hipStream_t);
+template void resid_restrict<double>(const OpView<double> &, const double *, const double *,
+                                     double *, hipStream_t);
+template void prolong_add<float>(int, int, const float *, float *, hipStream_t);
+template void prolong_add<double>(int, int, const double *, double *, hipStream_t);
+template void dense_solve<float>(const float *, int, const float *, float *, hipStream_t);
+template void dense_solve<double>(const double *, int, const double *, double *, hipStream_t);
+template void spmm_dots<float>(const OpView<double> &, const float *, const double *, int,
+                               const double *, const double *, const KrylovState *, int, double *,
+                               hipStream_t);
+template void spmm_dots<double>(const OpView<double> &, const double *, const double *, int,
+                                const double *, const double *, const KrylovState *, int,
+                                double *, hipStream_t);
+template void spmm_update<float>(const OpView<double> &, const float *, const double *, int,
+                                 const double *, const double *, const double *,
+                                 const KrylovState *, double *, double *, hipStream_t);
+template void spmm_update<double>(const OpView<double> &, const double *, const double *, int,
+                                  const double *, const double *, const double *,
+                                  const KrylovState *, double *, double *, hipStream_t);
+template void accumulate_solution<float>(const float *, size_t, const double *, int, size_t,
+                                         double *, hipStream_t);
+template void accumulate_solution<double>(const double *, size_t, const double *, int, size_t,
+                                          double *, hipStream_t);
+
+}  // namespace kern
+}  // namespace irk

@@ -1,0 +1,150 @@
+// Device kernels of the IRK stage solver (gfx950, wave64) and their host
+// launchers.  All launches go to the stream passed in; nothing synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace irk {
+
+constexpr int kBlock = 256;  // threads per block for point kernels (4 waves)
+constexpr int kMaxStages = 8;
+
+// A stencil operator on one grid level, as seen by the kernels.
+//  cls != nullptr: constant-coefficient operator; cls[q * 9 + k] is
+//                  coefficient k of boundary class q (see node_class).
+//  arr != nullptr: per-node coefficients, arr[k * N + p].
+//  npt = 5: only the centre and the four edge neighbours are nonzero.
+template <typename T>
+struct OpView {
+  int nx, ny;
+  int npt;
+  const T *cls;
+  const T *arr;
+};
+
+// Scalars the Krylov kernels read from device memory so that a whole
+// iteration can be replayed without host arguments changing.
+struct KrylovState {
+  int j;          // current iteration (column) index within the cycle
+  int converged;  // set by the Givens kernel
+  int breakdown;  // set by the Givens kernel
+  int pad;
+};
+
+namespace kern {
+
+// f = g - K u (g may be null); V0[i*N + p] = f[p] for every stage i; per-block
+// partial sums of f^2 into partial[blk].  nblk = ceil(N / kBlock).
+void rhs_forward(const OpView<double> &K, const double *u, const double *g, int s, double *f,
+                 double *V0, double *partial, hipStream_t st);
+
+// V0 = given stage-major rhs (copy), partial sums of rhs^2.
+void rhs_copy(const double *rhs, size_t n, double *V0, double *partial, hipStream_t st);
+
+// scale[col] = 1 / sqrt(sum partial) (and norm_out = sqrt(sum) if non-null);
+// single block.
+void finalize_norm(const double *partial, int nblk, double *scale, int col, double *norm_out,
+                   hipStream_t st);
+
+// Block-substitution coupling for stage i of the preconditioner (Sec. 4.2):
+//   b = scale_j * v_i - K( sum_{k in done} C[i*s+k] z_k )
+// v = V_j (double, stage-major, lazily scaled by *scale_j); z = Z_j (T).
+template <typename T>
+void couple(const OpView<T> &K, const double *v, const double *scale_j, const T *z,
+            const double *C, int s, int i, T *b, hipStream_t st);
+
+// Red-black Gauss-Seidel half sweep on colour ((i + j) % 2 == color) of
+// D x = b.  zero_init: x was zero, so x_c = b_c / d_c and the other colour is
+// written as zero.
+template <typename T>
+void rb_sweep(const OpView<T> &D, T *x, const T *b, int color, int zero_init, hipStream_t st);
+
+// rc[I] = sum over the 2x2 aggregate of (b - D x).
+template <typename T>
+void resid_restrict(const OpView<T> &D, const T *x, const T *b, T *rc, hipStream_t st);
+
+// x += P ec (cell-centred bilinear interpolation from the coarse grid).
+template <typename T>
+void prolong_add(int nx, int ny, const T *ec, T *x, hipStream_t st);
+
+// x = Cinv b, dense n x n (row-major), the coarsest-level solve.
+template <typename T>
+void dense_solve(const T *Cinv, int n, const T *b, T *x, hipStream_t st);
+
+// Kronecker SpMM with fused classical Gram-Schmidt dots:
+//   w = z + (hA (x) K) z  (M = I), z = Z_j (TZ, stage-major)
+//   partial[m * nblk + blk] = block sum of <V_m, w> * scale_m, m = 0..j
+template <typename TZ>
+void spmm_dots(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
+               const double *scale, const KrylovState *ks, int jmax, double *partial,
+               hipStream_t st);
+
+// w = z + (hA (x) K) z recomputed; vout = w - sum_{m<=j} hcol[m] scale_m V_m;
+// partial[blk] = block sum of vout^2.
+template <typename TZ>
+void spmm_update(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
+                 const double *scale, const double *hcol, const KrylovState *ks, double *vout,
+                 double *partial, hipStream_t st);
+
+// Second Gram-Schmidt pass: partial dots of vin with V_0..V_j.
+void vec_dots(const double *vin, size_t n, const double *V, const double *scale,
+              const KrylovState *ks, int jmax, double *partial, hipStream_t st);
+// vin -= sum_m h2[m] scale_m V_m; partial norms.
+void vec_update(double *vin, size_t n, const double *V, const double *scale, const double *h2,
+                const KrylovState *ks, double *partial, hipStream_t st);
+
+// out[m] = sum_b partial[m * nblk + b] for m = 0..j (one block per column).
+void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, double *out,
+                 hipStream_t st);
+
+// Single-block Hessenberg/Givens step for column j (see solver).
+void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
+            double *H, int ldh, double *cs, double *sn, double *g, double *scale,
+            KrylovState *ks, double beta, double rtol, double *host_resid, hipStream_t st);
+
+// Back substitution H y = g for the leading k x k block, single block.
+void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);
+
+// acc (double, s*N) += sum_{j<k} y_j Z_j  (Z stride zs elements per column).
+template <typename TZ>
+void accumulate_solution(const TZ *Z, size_t zs, const double *y, int k, size_t n, double *acc,
+                         hipStream_t st);
+
+// u_out = u_in + sum_i wts[i] * x_i   (x stage-major double, wts = h b).
+void combine_stages(const double *u_in, const double *x, const double *wts, int s, size_t N,
+                    double *u_out, hipStream_t st);
+
+// r = rhs - (I + hA (x) K) x; V0 = r; partial norms.  rhs == nullptr with f
+// given means rhs = 1 (x) f.
+void residual_full(const OpView<double> &K, const double *x, const double *hA, int s,
+                   const double *rhs, const double *f, double *V0, double *partial,
+                   hipStream_t st);
+
+// y = (I + hA (x) K) x for a double stage-major x (the Kronecker SpMM alone).
+void kron_apply(const OpView<double> &K, const double *x, const double *hA, int s, double *y,
+                hipStream_t st);
+
+// Stage values U_i = u + sum_j hA[i][j] k_j.
+void stage_values(const double *u, const double *k, const double *hA, int s, size_t N, double *U,
+                  hipStream_t st);
+
+// lam_out = lam_in - K^T sum_i psi_i (K symmetric: K^T = K).
+void adjoint_lambda(const OpView<double> &K, const double *lam_in, const double *psi, int s,
+                    double *lam_out, hipStream_t st);
+
+// rhs = wts (x) lam  (wts = h b), stage-major.
+void scaled_broadcast(const double *lam, const double *wts, int s, size_t N, double *rhs,
+                      hipStream_t st);
+
+// Nodal gradient of the face-diffusion operator, accumulated into gnode
+// ((nx+2) x (ny+2)): every face (P,Q) adds -1/2 h^-2 sum_i (psi_iP -
+// psi_iQ)(U_iP - U_iQ) to both nodes.
+void grad_nodes(const double *psi, const double *U, int s, int nx, int ny, double inv_h2,
+                double *gnode, hipStream_t st);
+
+// Count of non-finite entries (nonzero result = bad), via partial sums.
+void nonfinite_check(const double *x, size_t n, double *partial, hipStream_t st);
+
+}  // namespace kern
+}  // namespace irk

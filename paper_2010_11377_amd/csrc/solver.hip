@@ -1,0 +1,938 @@
+// Host runtime of libirk: setup of the block preconditioner and its AMG
+// hierarchy, the flexible GMRES loop, and the C ABI of include/irk.h.
+//
+// Per Krylov iteration j (right preconditioning, flexible):
+//   z_j = P^-1 v_j                 block substitution over the stages
+//                                  (Sec. 4.2), one V-cycle per stage block
+//   w   = (I + hA (x) K) z_j       Kronecker SpMM, dots with V_0..V_j fused
+//   v_{j+1} = w - sum h_mj v_m     classical Gram-Schmidt (+ optional second
+//                                  pass), recomputing w instead of storing it
+//   Givens update of the Hessenberg column and |g_{j+1}| (single block)
+// The residual estimate is read on the host once per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/irk.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using irk::KrylovState;
+using irk::OpView;
+using irk::Stencil9;
+
+namespace {
+
+template <typename T>
+struct DevOp {
+  int nx = 0, ny = 0, npt = 9;
+  T *cls = nullptr;
+  T *arr = nullptr;
+  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr}; }
+};
+
+struct HipError {
+  hipError_t e;
+  const char *what;
+};
+
+#define HIP_TRY(expr)                            \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) throw HipError{_e, #expr}; \
+  } while (0)
+
+}  // namespace
+
+struct irk_solver {
+  hipStream_t stream = nullptr;
+  int s = 0, nx = 0, ny = 0;
+  size_t N = 0, sN = 0;
+  double h = 0.0;
+  double A[64] = {}, b[8] = {}, At[64] = {};
+  double hA[64] = {}, hAT[64] = {};
+  double Cfwd[64] = {}, Cadj[64] = {};
+  int ord_fwd[8] = {}, ord_adj[8] = {};
+  double tau[8] = {}, hb[8] = {};
+  irk_options opt{};
+  bool const_mode = false, symmetric = false;
+  int nlev = 0, ncoarse = 0;
+  std::vector<int> lnx, lny;
+
+  // operators (rebuilt by irk_update_operator)
+  DevOp<double> K64;
+  DevOp<float> K32;
+  std::vector<std::vector<DevOp<double>>> D64;  // [stage][level]
+  std::vector<std::vector<DevOp<float>>> D32;
+  std::vector<double *> Cinv64;
+  std::vector<float *> Cinv32;
+  std::vector<void *> op_allocs;
+
+  // workspace
+  double *V = nullptr, *acc = nullptr, *f = nullptr, *g = nullptr, *rhs = nullptr;
+  double *Ubuf = nullptr, *zero = nullptr, *gbuf = nullptr;
+  double *partial = nullptr, *pnorm = nullptr;
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *y = nullptr;
+  double *scale = nullptr, *h1 = nullptr, *h2 = nullptr, *norm_dev = nullptr;
+  double *dev_resid = nullptr;
+  double *host_resid = nullptr;  // pinned
+  void *Z = nullptr;             // m * sN elements of float or double
+  void *b0 = nullptr;            // level-0 right-hand side, N elements
+  void *levb = nullptr, *levx = nullptr;
+  std::vector<size_t> lev_off;
+  KrylovState *ks = nullptr;
+  size_t partial_len = 0;
+  std::vector<void *> ws_allocs;
+
+  // measurement hook (irk_profile_select / irk_profile_read)
+  struct ProfTok {
+    hipEvent_t a = nullptr, b = nullptr;
+    double bytes = 0.0;
+  };
+  int prof_sel = -1;
+  std::vector<hipEvent_t> prof_pool;
+  std::vector<ProfTok> prof_pending;
+  long long prof_launches = 0;
+  double prof_ms = 0.0, prof_bytes = 0.0;
+
+  std::string err;
+};
+
+namespace {
+
+size_t elem_size(const irk_solver *S) { return S->opt.precision == IRK_MIXED ? 4 : 8; }
+
+using ProfTok = irk_solver::ProfTok;
+
+hipEvent_t prof_event(irk_solver *S) {
+  if (!S->prof_pool.empty()) {
+    hipEvent_t e = S->prof_pool.back();
+    S->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_TRY(hipEventCreate(&e));
+  return e;
+}
+
+// Start timing a launch of kernel class kc (no-op unless kc is selected).
+ProfTok prof_begin(irk_solver *S, int kc, double bytes) {
+  ProfTok t;
+  if (S->prof_sel != kc) return t;
+  t.a = prof_event(S);
+  t.b = prof_event(S);
+  t.bytes = bytes;
+  HIP_TRY(hipEventRecord(t.a, S->stream));
+  return t;
+}
+
+void prof_end(irk_solver *S, const ProfTok &t) {
+  if (!t.a) return;
+  HIP_TRY(hipEventRecord(t.b, S->stream));
+  S->prof_pending.push_back(t);
+}
+
+// Resolve the recorded events; call only after the stream has synchronised.
+void prof_collect(irk_solver *S) {
+  for (const ProfTok &t : S->prof_pending) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    S->prof_ms += ms;
+    S->prof_bytes += t.bytes;
+    S->prof_launches += 1;
+    S->prof_pool.push_back(t.a);
+    S->prof_pool.push_back(t.b);
+  }
+  S->prof_pending.clear();
+}
+
+// Coefficient bytes of one pass over a stored operator (0 for a constant one).
+double op_bytes(const irk_solver *S, size_t n, int npt, size_t es) {
+  return S->const_mode ? 0.0 : (double)n * npt * es;
+}
+
+template <typename T>
+T *dalloc(std::vector<void *> &list, size_t n) {
+  void *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+  list.push_back(p);
+  return static_cast<T *>(p);
+}
+
+template <typename T>
+DevOp<T> upload_op(irk_solver *S, const Stencil9 &op, bool use_classes, int npt) {
+  DevOp<T> d;
+  d.nx = op.nx;
+  d.ny = op.ny;
+  d.npt = npt;
+  if (use_classes) {
+    double cls[9][9];
+    irk::classify(op, 1e-12, cls);
+    std::vector<T> h(81);
+    for (int q = 0; q < 9; ++q)
+      for (int k = 0; k < 9; ++k) h[q * 9 + k] = (T)cls[q][k];
+    d.cls = dalloc<T>(S->op_allocs, 81);
+    HIP_TRY(hipMemcpy(d.cls, h.data(), 81 * sizeof(T), hipMemcpyHostToDevice));
+  } else {
+    const size_t n = op.size();
+    std::vector<T> h(9 * n);
+    for (int k = 0; k < 9; ++k)
+      for (size_t p = 0; p < n; ++p) h[(size_t)k * n + p] = (T)op.c[k][p];
+    d.arr = dalloc<T>(S->op_allocs, 9 * n);
+    HIP_TRY(hipMemcpy(d.arr, h.data(), 9 * n * sizeof(T), hipMemcpyHostToDevice));
+  }
+  return d;
+}
+
+int stencil_npt(const Stencil9 &op) {
+  for (int k : {0, 2, 6, 8})
+    for (double v : op.c[k])
+      if (v != 0.0) return 9;
+  return 5;
+}
+
+void free_list(std::vector<void *> &list) {
+  for (void *p : list) (void)hipFree(p);
+  list.clear();
+}
+
+// Build the operators: K on the fine grid and, for every stage block
+// D_i = I + tau_i K (Sec. 4.2), the Galerkin hierarchy S_l + tau_i K_l and the
+// dense inverse on the coarsest level.
+irk_status build_operators(irk_solver *S, const irk_csr *K) {
+  Stencil9 K0;
+  if (!irk::csr_to_stencil(K->n, K->rowptr, K->colind, K->val, S->nx, S->ny, K0, S->err))
+    return IRK_E_INVALID;
+  S->symmetric = irk::is_symmetric(K0, 1e-13);
+  // hierarchy of S_l = R S_{l-1} P (S_0 = I) and K_l = R K_{l-1} P
+  std::vector<Stencil9> Sl, Kl;
+  Sl.push_back(irk::identity_stencil(S->nx, S->ny));
+  Kl.push_back(K0);
+  while ((long long)Sl.back().nx * Sl.back().ny > S->opt.coarse_max && Sl.back().nx % 2 == 0 &&
+         Sl.back().ny % 2 == 0 && Sl.back().nx >= 2 && Sl.back().ny >= 2) {
+    Sl.push_back(irk::galerkin(Sl.back()));
+    Kl.push_back(irk::galerkin(Kl.back()));
+  }
+  const int L = (int)Sl.size();
+  const long long ncoarse = (long long)Sl.back().nx * Sl.back().ny;
+  if (ncoarse > 1024) {
+    S->err = "the grid does not coarsen to at most 1024 unknowns by halving (nx, ny must stay "
+             "even down to coarse_max)";
+    return IRK_E_INVALID;
+  }
+  bool cm = true;
+  double tmp[9][9];
+  for (int l = 0; l < L && cm; ++l) cm = irk::classify(Sl[l], 1e-12, tmp) && irk::classify(Kl[l], 1e-12, tmp);
+  S->const_mode = cm;
+  S->nlev = L;
+  S->ncoarse = (int)ncoarse;
+  S->lnx.clear();
+  S->lny.clear();
+  for (int l = 0; l < L; ++l) {
+    S->lnx.push_back(Sl[l].nx);
+    S->lny.push_back(Sl[l].ny);
+  }
+  free_list(S->op_allocs);
+  S->D64.assign(S->s, {});
+  S->D32.assign(S->s, {});
+  S->Cinv64.assign(S->s, nullptr);
+  S->Cinv32.assign(S->s, nullptr);
+  const bool mixed = S->opt.precision == IRK_MIXED;
+  const int npt0 = stencil_npt(K0);
+  S->K64 = upload_op<double>(S, K0, cm, npt0);
+  if (mixed) S->K32 = upload_op<float>(S, K0, cm, npt0);
+  for (int i = 0; i < S->s; ++i) {
+    for (int l = 0; l + 1 < L; ++l) {
+      Stencil9 D = irk::axpy_stencil(Sl[l], S->tau[i], Kl[l]);
+      const int npt = stencil_npt(D);
+      if (mixed)
+        S->D32[i].push_back(upload_op<float>(S, D, cm, npt));
+      else
+        S->D64[i].push_back(upload_op<double>(S, D, cm, npt));
+    }
+    Stencil9 Dc = irk::axpy_stencil(Sl[L - 1], S->tau[i], Kl[L - 1]);
+    std::vector<double> inv;
+    if (!irk::dense_inverse(Dc, inv)) {
+      S->err = "singular coarsest-level block";
+      return IRK_E_INVALID;
+    }
+    const size_t nn = inv.size();
+    if (mixed) {
+      std::vector<float> hf(inv.begin(), inv.end());
+      S->Cinv32[i] = dalloc<float>(S->op_allocs, nn);
+      HIP_TRY(hipMemcpy(S->Cinv32[i], hf.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      S->Cinv64[i] = dalloc<double>(S->op_allocs, nn);
+      HIP_TRY(hipMemcpy(S->Cinv64[i], inv.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
+  return IRK_OK;
+}
+
+void alloc_workspace(irk_solver *S) {
+  const int m = S->opt.restart;
+  const size_t N = S->N, sN = S->sN;
+  auto &L = S->ws_allocs;
+  S->V = dalloc<double>(L, (size_t)(m + 1) * sN);
+  S->Z = (S->opt.precision == IRK_MIXED) ? (void *)dalloc<float>(L, (size_t)m * sN)
+                                         : (void *)dalloc<double>(L, (size_t)m * sN);
+  S->acc = dalloc<double>(L, sN);
+  S->rhs = dalloc<double>(L, sN);
+  S->f = dalloc<double>(L, N);
+  S->g = nullptr;
+  S->zero = dalloc<double>(L, sN);
+  HIP_TRY(hipMemset(S->zero, 0, sN * sizeof(double)));
+  const size_t nblk_pt = (N + irk::kBlock - 1) / irk::kBlock;
+  const size_t nblk_vec = (sN + irk::kBlock * 4 - 1) / (irk::kBlock * 4);
+  const size_t nblk_full = (sN + irk::kBlock - 1) / irk::kBlock;
+  S->partial_len = std::max({(size_t)(m + 2) * std::max(nblk_pt, nblk_vec), nblk_full,
+                             (size_t)((S->nx + 2) * (size_t)(S->ny + 2) / irk::kBlock + 2)});
+  S->partial = dalloc<double>(L, S->partial_len);
+  S->pnorm = dalloc<double>(L, std::max({nblk_pt, nblk_vec, nblk_full}));
+  S->H = dalloc<double>(L, (size_t)(m + 1) * m);
+  S->cs = dalloc<double>(L, m + 1);
+  S->sn = dalloc<double>(L, m + 1);
+  S->gv = dalloc<double>(L, m + 2);
+  S->y = dalloc<double>(L, m + 1);
+  S->scale = dalloc<double>(L, m + 2);
+  S->h1 = dalloc<double>(L, m + 2);
+  S->h2 = dalloc<double>(L, m + 2);
+  S->norm_dev = dalloc<double>(L, 2);
+  S->dev_resid = dalloc<double>(L, 2);
+  S->ks = dalloc<KrylovState>(L, 1);
+  const size_t es = elem_size(S);
+  S->b0 = dalloc<char>(L, N * es);
+  size_t tot = 0;
+  S->lev_off.assign(S->nlev + 1, 0);
+  for (int l = 1; l < S->nlev; ++l) {
+    S->lev_off[l] = tot;
+    tot += (size_t)S->lnx[l] * S->lny[l];
+  }
+  S->levb = dalloc<char>(L, (tot + 1) * es);
+  S->levx = dalloc<char>(L, (tot + 1) * es);
+  void *hp = nullptr;
+  HIP_TRY(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault));
+  S->host_resid = static_cast<double *>(hp);
+}
+
+template <typename T>
+const std::vector<std::vector<DevOp<T>>> &Dops(const irk_solver *S);
+template <>
+const std::vector<std::vector<DevOp<double>>> &Dops<double>(const irk_solver *S) {
+  return S->D64;
+}
+template <>
+const std::vector<std::vector<DevOp<float>>> &Dops<float>(const irk_solver *S) {
+  return S->D32;
+}
+template <typename T>
+const T *Cinv(const irk_solver *S, int i);
+template <>
+const double *Cinv<double>(const irk_solver *S, int i) {
+  return S->Cinv64[i];
+}
+template <>
+const float *Cinv<float>(const irk_solver *S, int i) {
+  return S->Cinv32[i];
+}
+template <typename T>
+OpView<T> Kview(const irk_solver *S);
+template <>
+OpView<double> Kview<double>(const irk_solver *S) {
+  return S->K64.view();
+}
+template <>
+OpView<float> Kview<float>(const irk_solver *S) {
+  return S->K32.view();
+}
+
+// One V-cycle for the stage-i block on level l: x ~= D_il^-1 b (x is overwritten).
+template <typename T>
+void vcycle(irk_solver *S, int i, int l, const T *b, T *x) {
+  hipStream_t st = S->stream;
+  if (l == S->nlev - 1) {
+    ProfTok t = prof_begin(S, IRK_KC_COARSE,
+                           (double)S->ncoarse * (S->ncoarse + 2.0) * sizeof(T));
+    irk::kern::dense_solve<T>(Cinv<T>(S, i), S->ncoarse, b, x, st);
+    prof_end(S, t);
+    return;
+  }
+  const DevOp<T> &D = Dops<T>(S)[i][l];
+  const OpView<T> v = D.view();
+  const int nc = (D.npt == 5) ? 2 : 4;
+  const size_t n = (size_t)D.nx * D.ny, es = sizeof(T);
+  const int kc_s = (l == 0) ? IRK_KC_SMOOTH_L0 : IRK_KC_COARSE;
+  const int kc_r = (l == 0) ? IRK_KC_RESTRICT_L0 : IRK_KC_COARSE;
+  const int kc_p = (l == 0) ? IRK_KC_PROLONG_L0 : IRK_KC_COARSE;
+  const double cb = op_bytes(S, n, D.npt, es);
+  if (S->opt.nu_pre <= 0) HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(T), st));
+  for (int sw = 0; sw < S->opt.nu_pre; ++sw)
+    for (int c = 0; c < nc; ++c) {
+      const bool z0 = (sw == 0 && c == 0);
+      // one colour: read b and the neighbours of that colour's nodes, write it
+      // (a zero start reads b of the colour and writes every node)
+      ProfTok t = prof_begin(S, kc_s, z0 ? (double)n * es * (1.0 / nc + 1.0)
+                                         : (double)n * es * (1.0 + 2.0 / nc) + cb / nc);
+      irk::kern::rb_sweep<T>(v, x, b, c, z0 ? 1 : 0, st);
+      prof_end(S, t);
+    }
+  T *bc = static_cast<T *>(S->levb) + S->lev_off[l + 1];
+  T *xc = static_cast<T *>(S->levx) + S->lev_off[l + 1];
+  {
+    ProfTok t = prof_begin(S, kc_r, (double)n * es * 2.25 + cb);
+    irk::kern::resid_restrict<T>(v, x, b, bc, st);
+    prof_end(S, t);
+  }
+  vcycle<T>(S, i, l + 1, bc, xc);
+  {
+    ProfTok t = prof_begin(S, kc_p, (double)n * es * 2.25);
+    irk::kern::prolong_add<T>(D.nx, D.ny, xc, x, st);
+    prof_end(S, t);
+  }
+  for (int sw = 0; sw < S->opt.nu_post; ++sw)
+    for (int c = nc - 1; c >= 0; --c) {
+      ProfTok t = prof_begin(S, kc_s, (double)n * es * (1.0 + 2.0 / nc) + cb / nc);
+      irk::kern::rb_sweep<T>(v, x, b, c, 0, st);
+      prof_end(S, t);
+    }
+}
+
+// z = P^-1 v by block substitution (Sec. 4.2).  v = V_j (lazy scale
+// scale[j]), z = Z_j.  C holds h A~ without its diagonal, ord the stage order.
+template <typename T>
+void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, const double *C,
+                   const int *ord) {
+  T *b0 = static_cast<T *>(S->b0);
+  for (int t = 0; t < S->s; ++t) {
+    const int i = ord[t];
+    int ncoup = 0;
+    for (int k = 0; k < S->s; ++k) ncoup += (C[(size_t)i * S->s + k] != 0.0);
+    // v_i (double), the coupled z_k and the output b
+    ProfTok tk = prof_begin(S, IRK_KC_COUPLE,
+                            (double)S->N * (8.0 + sizeof(T) * (ncoup + 1)) +
+                                (ncoup ? op_bytes(S, S->N, S->K64.npt, sizeof(T)) : 0.0));
+    irk::kern::couple<T>(Kview<T>(S), v, scale_j, z, C + (size_t)i * S->s, S->s, i, b0, S->stream);
+    prof_end(S, tk);
+    vcycle<T>(S, i, 0, b0, z + (size_t)i * S->N);
+  }
+}
+
+struct SystemDesc {
+  const double *hA;  // s x s matrix of the SpMM (h A or h A^T)
+  const double *C;   // coupling h A~ without diagonal (row i = stage i)
+  const int *ord;    // substitution order
+  // right-hand side: forward = 1 (x) (g - K u); otherwise rhs (s*N) given
+  const double *u;
+  bool forward;
+};
+
+template <typename T>
+irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
+  using namespace irk::kern;
+  hipStream_t st = S->stream;
+  const int s = S->s, m = S->opt.restart;
+  const size_t N = S->N, sN = S->sN;
+  const int nblk_pt = (int)((N + irk::kBlock - 1) / irk::kBlock);
+  const int nblk_vec = (int)((sN + irk::kBlock * 4 - 1) / (irk::kBlock * 4));
+  const int nblk_full = (int)((sN + irk::kBlock - 1) / irk::kBlock);
+  const OpView<double> K = S->K64.view();
+  T *Z = static_cast<T *>(S->Z);
+
+  HIP_TRY(hipMemsetAsync(S->acc, 0, sN * sizeof(double), st));
+  // initial residual = rhs (x0 = 0)
+  if (sys.forward) {
+    rhs_forward(K, sys.u, S->g, s, S->f, S->V, S->partial, st);
+    finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
+  } else {
+    rhs_copy(S->rhs, sN, S->V, S->partial, st);
+    finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
+  }
+  HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double beta0 = S->host_resid[0];
+  if (stats) {
+    stats->iters = 0;
+    stats->restarts = 0;
+    stats->rel_resid_est = 0.0;
+    stats->rel_resid_true = -1.0;
+  }
+  if (!std::isfinite(beta0)) {
+    S->err = "non-finite right-hand side";
+    return IRK_E_NONFINITE;
+  }
+  if (beta0 == 0.0) return IRK_OK;  // k = 0 solves the system exactly
+
+  double beta = beta0;
+  int total = 0, restarts = 0;
+  irk_status status = IRK_E_NOT_CONVERGED;
+  double est = 1.0;
+  while (true) {
+    KrylovState ks0{0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(S->ks, &ks0, sizeof ks0, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(S->gv, &beta, sizeof(double), hipMemcpyHostToDevice, st));
+    int j = 0;
+    bool stop = false;
+    for (; j < m; ++j) {
+      const double *Vj = S->V + (size_t)j * sN;
+      T *Zj = Z + (size_t)j * sN;
+      apply_precond<T>(S, Vj, S->scale + j, Zj, sys.C, sys.ord);
+      const double kb = op_bytes(S, N, S->K64.npt, 8);
+      const double zb = (double)sN * sizeof(T), vb = (double)sN * 8.0;
+      ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb);
+      spmm_dots<T>(K, Z, sys.hA, s, S->V, S->scale, S->ks, j, S->partial, st);
+      prof_end(S, t1);
+      reduce_cols(S->partial, nblk_pt, S->ks, j, S->h1, st);
+      ProfTok t2 = prof_begin(S, IRK_KC_SPMM_UPDATE, zb + vb * (j + 2) + kb);
+      spmm_update<T>(K, Z, sys.hA, s, S->V, S->scale, S->h1, S->ks, S->V, S->pnorm, st);
+      prof_end(S, t2);
+      int nblk_norm = nblk_pt;
+      const double *h2 = nullptr;
+      // second classical Gram-Schmidt pass (CGS2) for a well-conditioned basis
+      ProfTok t3 = prof_begin(S, IRK_KC_VEC_DOTS, vb * (j + 2));
+      vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
+      prof_end(S, t3);
+      reduce_cols(S->partial, nblk_vec, S->ks, j, S->h2, st);
+      ProfTok t4 = prof_begin(S, IRK_KC_VEC_UPDATE, vb * (j + 3));
+      vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm, st);
+      prof_end(S, t4);
+      nblk_norm = nblk_vec;
+      h2 = S->h2;
+      givens(S->h1, h2, S->pnorm, nblk_norm, S->H, m + 1, S->cs, S->sn, S->gv, S->scale, S->ks,
+             beta0, S->opt.rtol, S->dev_resid, st);
+      HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      prof_collect(S);
+      ++total;
+      const double res = S->host_resid[0];
+      const int brk = (int)S->host_resid[1];
+      est = res / beta0;
+      if (brk == 1 || !std::isfinite(res)) {
+        status = IRK_E_BREAKDOWN;
+        S->err = "Krylov breakdown (non-finite or zero Hessenberg entry)";
+        stop = true;
+        ++j;
+        break;
+      }
+      if (res <= S->opt.rtol * beta0 || brk == 2) {
+        status = IRK_OK;
+        stop = true;
+        ++j;
+        break;
+      }
+      if (total >= S->opt.max_iter) {
+        status = IRK_E_NOT_CONVERGED;
+        stop = true;
+        ++j;
+        break;
+      }
+    }
+    // x += Z y over the j columns of this cycle (a column that broke down is dropped)
+    if (status == IRK_E_BREAKDOWN) --j;
+    solve_upper(S->H, m + 1, S->gv, j, S->y, st);
+    accumulate_solution<T>(Z, sN, S->y, j, sN, S->acc, st);
+    if (stop) break;
+    // restart from the true residual
+    ++restarts;
+    residual_full(K, S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V, S->partial, st);
+    finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
+    HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    beta = S->host_resid[0];
+    est = beta / beta0;
+    if (!(beta > S->opt.rtol * beta0)) {
+      status = std::isfinite(beta) ? IRK_OK : IRK_E_NONFINITE;
+      break;
+    }
+  }
+  if (stats) {
+    stats->iters = total;
+    stats->restarts = restarts;
+    stats->rel_resid_est = est;
+  }
+  if (S->opt.true_resid && stats) {
+    residual_full(K, S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V, S->partial, st);
+    finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
+    HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    stats->rel_resid_true = S->host_resid[0] / beta0;
+  }
+  return status;
+}
+
+irk_status run_system(irk_solver *S, const SystemDesc &sys, irk_stats *st) {
+  if (S->opt.precision == IRK_MIXED) return fgmres<float>(S, sys, st);
+  return fgmres<double>(S, sys, st);
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+bool valid_options(const irk_options &o, std::string &err) {
+  if (o.precision != IRK_FP64 && o.precision != IRK_MIXED) return err = "bad precision", false;
+  if (o.precond < IRK_PREC_LD || o.precond > IRK_PREC_J) return err = "bad precond", false;
+  if (o.restart < 1 || o.restart > 200) return err = "restart must be in 1..200", false;
+  if (o.max_iter < 1) return err = "max_iter must be >= 1", false;
+  if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre > 8 || o.nu_post > 8)
+    return err = "nu_pre/nu_post must be in 0..8", false;
+  if (o.coarse_max < 1) return err = "coarse_max must be >= 1", false;
+  if (o.vcycles != 1) return err = "only one V-cycle per subsolve is implemented", false;
+  if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return err = "rtol must be in (0, 1)", false;
+  return true;
+}
+
+thread_local std::string g_setup_error;
+
+template <typename F>
+irk_status guarded(irk_solver *S, F &&fn) {
+  try {
+    return fn();
+  } catch (const HipError &e) {
+    if (S) {
+      S->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+    }
+    return e.e == hipErrorOutOfMemory ? IRK_E_OOM : IRK_E_HIP;
+  } catch (const std::bad_alloc &) {
+    if (S) S->err = "host allocation failed";
+    return IRK_E_OOM;
+  } catch (...) {
+    if (S) S->err = "unexpected exception";
+    return IRK_E_INVALID;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void irk_default_options(irk_options *o) {
+  if (!o) return;
+  o->precision = IRK_FP64;
+  o->precond = IRK_PREC_LD;
+  o->restart = 40;
+  o->max_iter = 200;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->coarse_max = 256;
+  o->vcycles = 1;
+  o->true_resid = 0;
+  o->rtol = 1e-8;
+}
+
+irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {
+  int rc = irk::ldu_factor(s, A, L, d, U);
+  return rc == 0 ? IRK_OK : (rc == -2 ? IRK_E_SINGULAR_PIVOT : IRK_E_INVALID);
+}
+
+irk_status irk_setup(irk_solver **out, const irk_butcher *tab, const irk_csr *M, const irk_csr *K,
+                     double h_t, const irk_grid *grid, const irk_options *opt, void *hip_stream) {
+  if (!out) return IRK_E_INVALID;
+  *out = nullptr;
+  irk_solver *S = new (std::nothrow) irk_solver();
+  if (!S) return IRK_E_OOM;
+  irk_status rc = guarded(S, [&]() -> irk_status {
+    if (!tab || !tab->A || !tab->b || tab->s < 1 || tab->s > 8) {
+      S->err = "bad Butcher tableau (need 1 <= s <= 8 and non-null A, b)";
+      return IRK_E_INVALID;
+    }
+    if (M) {
+      S->err = "only M = I is supported (pass M = NULL)";
+      return IRK_E_INVALID;
+    }
+    if (!K || !grid) {
+      S->err = "K and the structured grid are required";
+      return IRK_E_INVALID;
+    }
+    if (!(h_t > 0.0) || !std::isfinite(h_t)) {
+      S->err = "h_t must be positive and finite";
+      return IRK_E_INVALID;
+    }
+    irk_options o;
+    irk_default_options(&o);
+    if (opt) o = *opt;
+    if (!valid_options(o, S->err)) return IRK_E_INVALID;
+    S->opt = o;
+    S->stream = static_cast<hipStream_t>(hip_stream);
+    S->s = tab->s;
+    S->nx = grid->nx;
+    S->ny = grid->ny;
+    if (S->nx < 1 || S->ny < 1 || (long long)S->nx * S->ny != K->n) {
+      S->err = "grid size does not match K";
+      return IRK_E_INVALID;
+    }
+    S->N = (size_t)S->nx * S->ny;
+    S->sN = S->N * S->s;
+    S->h = h_t;
+    const int s = S->s;
+    for (int i = 0; i < s * s; ++i) {
+      S->A[i] = tab->A[i];
+      if (!std::isfinite(S->A[i])) {
+        S->err = "non-finite Butcher coefficient";
+        return IRK_E_INVALID;
+      }
+    }
+    for (int i = 0; i < s; ++i) S->b[i] = tab->b[i];
+    // A~ and its LDU (Sec. 4.1): pivot check for every choice
+    if (irk::ldu_factor(s, S->A, nullptr, nullptr, nullptr) == -2) {
+      S->err = "A has a zero leading principal minor: no LDU factorisation without pivoting";
+      return IRK_E_SINGULAR_PIVOT;
+    }
+    const int kind = o.precond;  // 0 LD, 1 DU, 2 GSL, 3 J
+    if (irk::coefficient_matrix(s, S->A, kind, S->At) != 0) {
+      S->err = "LDU factorisation failed";
+      return IRK_E_SINGULAR_PIVOT;
+    }
+    const bool upper = (kind == IRK_PREC_DU);
+    for (int i = 0; i < s; ++i) {
+      S->tau[i] = h_t * S->At[i * s + i];
+      S->hb[i] = h_t * S->b[i];
+      if (!(S->tau[i] > 0.0)) {
+        S->err = "a diagonal block I + h A~_ii K has A~_ii <= 0";
+        return IRK_E_INVALID;
+      }
+      for (int j = 0; j < s; ++j) {
+        S->hA[i * s + j] = h_t * S->A[i * s + j];
+        S->hAT[i * s + j] = h_t * S->A[j * s + i];
+        S->Cfwd[i * s + j] = (i == j) ? 0.0 : h_t * S->At[i * s + j];
+        S->Cadj[i * s + j] = (i == j) ? 0.0 : h_t * S->At[j * s + i];
+      }
+    }
+    for (int t = 0; t < s; ++t) {
+      S->ord_fwd[t] = upper ? s - 1 - t : t;  // lower: forward substitution
+      S->ord_adj[t] = upper ? t : s - 1 - t;  // transposed: the other direction
+    }
+    irk_status r = build_operators(S, K);
+    if (r != IRK_OK) return r;
+    alloc_workspace(S);
+    return IRK_OK;
+  });
+  if (rc != IRK_OK) {
+    // the solver is gone; its message stays readable through irk_last_error(NULL)
+    g_setup_error = S->err;
+    irk_destroy(S);
+    return rc;
+  }
+  g_setup_error.clear();
+  *out = S;
+  return IRK_OK;
+}
+
+irk_status irk_set_source(irk_solver *S, const double *g_dev) {
+  if (!S) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    if (!g_dev) {
+      S->g = nullptr;
+      return IRK_OK;
+    }
+    // the source lives in a buffer of its own, allocated on first use
+    if (!S->gbuf) S->gbuf = dalloc<double>(S->ws_allocs, S->N);
+    HIP_TRY(hipMemcpyAsync(S->gbuf, g_dev, S->N * sizeof(double), hipMemcpyDeviceToDevice,
+                           S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    S->g = S->gbuf;
+    return IRK_OK;
+  });
+}
+
+irk_status irk_update_operator(irk_solver *S, const irk_csr *K) {
+  if (!S || !K) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    if (K->n != (int)S->N) {
+      S->err = "K size changed";
+      return IRK_E_INVALID;
+    }
+    const int old_levels = S->nlev;
+    irk_status r = build_operators(S, K);
+    if (r == IRK_OK && S->nlev != old_levels) {
+      S->err = "hierarchy depth changed";
+      return IRK_E_INVALID;
+    }
+    return r;
+  });
+}
+
+static irk_status step_impl(irk_solver *S, const double *u_n, double *u_np1, double *k_out,
+                            irk_stats *st) {
+  if (!S || !u_n || !u_np1) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    const double t0 = now_s();
+    SystemDesc sys{S->hA, S->Cfwd, S->ord_fwd, u_n, true};
+    irk_stats local{};
+    irk_status r = run_system(S, sys, st ? st : &local);
+    if (r == IRK_OK || r == IRK_E_NOT_CONVERGED) {
+      irk::kern::combine_stages(u_n, S->acc, S->hb, S->s, S->N, u_np1, S->stream);
+      if (k_out)
+        HIP_TRY(hipMemcpyAsync(k_out, S->acc, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
+                               S->stream));
+      HIP_TRY(hipStreamSynchronize(S->stream));
+    }
+    if (st) st->seconds = now_s() - t0;
+    return r;
+  });
+}
+
+irk_status irk_step(irk_solver *S, const double *u_n_dev, double *u_np1_dev, irk_stats *st) {
+  return step_impl(S, u_n_dev, u_np1_dev, nullptr, st);
+}
+
+irk_status irk_step_stages(irk_solver *S, const double *u_n_dev, double *u_np1_dev, double *k_dev,
+                           irk_stats *st) {
+  if (!k_dev) return IRK_E_INVALID;
+  return step_impl(S, u_n_dev, u_np1_dev, k_dev, st);
+}
+
+irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *lam_np1_dev,
+                            double *lam_n_dev, double *psi_dev, double *U_dev, irk_stats *st) {
+  if (!S || !u_n_dev || !lam_np1_dev || !lam_n_dev) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    if (!S->symmetric) {
+      S->err = "the adjoint step needs a symmetric K";
+      return IRK_E_INVALID;
+    }
+    const double t0 = now_s();
+    irk_stats fst{}, ast{};
+    // 1. forward stages from the checkpoint u_n
+    SystemDesc fwd{S->hA, S->Cfwd, S->ord_fwd, u_n_dev, true};
+    irk_status r = run_system(S, fwd, &fst);
+    if (r != IRK_OK) return r;
+    if (!S->Ubuf) S->Ubuf = dalloc<double>(S->ws_allocs, S->sN);
+    irk::kern::stage_values(u_n_dev, S->acc, S->hA, S->s, S->N, S->Ubuf, S->stream);
+    // 2. transposed stage system with rhs h (b (x) lam_{n+1})
+    irk::kern::scaled_broadcast(lam_np1_dev, S->hb, S->s, S->N, S->rhs, S->stream);
+    SystemDesc adj{S->hAT, S->Cadj, S->ord_adj, nullptr, false};
+    r = run_system(S, adj, &ast);
+    if (r != IRK_OK && r != IRK_E_NOT_CONVERGED) return r;
+    // 3. lam_n = lam_{n+1} - K^T sum_i psi_i
+    irk::kern::adjoint_lambda(S->K64.view(), lam_np1_dev, S->acc, S->s, lam_n_dev, S->stream);
+    if (psi_dev)
+      HIP_TRY(hipMemcpyAsync(psi_dev, S->acc, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
+                             S->stream));
+    if (U_dev)
+      HIP_TRY(hipMemcpyAsync(U_dev, S->Ubuf, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
+                             S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    if (st) {
+      *st = ast;
+      st->iters = fst.iters + ast.iters;
+      st->seconds = now_s() - t0;
+    }
+    return r;
+  });
+}
+
+irk_status irk_grad_diffusion_nodes(irk_solver *S, const double *psi_dev, const double *U_dev,
+                                    double h_x, double *gnode_dev) {
+  if (!S || !psi_dev || !U_dev || !gnode_dev || !(h_x > 0.0)) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    irk::kern::grad_nodes(psi_dev, U_dev, S->s, S->nx, S->ny, 1.0 / (h_x * h_x), gnode_dev,
+                          S->stream);
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return IRK_OK;
+  });
+}
+
+irk_status irk_apply_operator(irk_solver *S, const double *x_dev, double *y_dev) {
+  if (!S || !x_dev || !y_dev) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    irk::kern::kron_apply(S->K64.view(), x_dev, S->hA, S->s, y_dev, S->stream);
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return IRK_OK;
+  });
+}
+
+irk_status irk_apply_preconditioner(irk_solver *S, const double *v_dev, double *z_dev) {
+  if (!S || !v_dev || !z_dev) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    const double one = 1.0;
+    HIP_TRY(hipMemcpyAsync(S->scale, &one, sizeof(double), hipMemcpyHostToDevice, S->stream));
+    HIP_TRY(hipMemcpyAsync(S->V, v_dev, S->sN * sizeof(double), hipMemcpyDeviceToDevice, S->stream));
+    HIP_TRY(hipMemcpyAsync(S->y, &one, sizeof(double), hipMemcpyHostToDevice, S->stream));
+    HIP_TRY(hipMemsetAsync(z_dev, 0, S->sN * sizeof(double), S->stream));
+    if (S->opt.precision == IRK_MIXED) {
+      apply_precond<float>(S, S->V, S->scale, static_cast<float *>(S->Z), S->Cfwd, S->ord_fwd);
+      irk::kern::accumulate_solution<float>(static_cast<float *>(S->Z), S->sN, S->y, 1, S->sN,
+                                            z_dev, S->stream);
+    } else {
+      apply_precond<double>(S, S->V, S->scale, static_cast<double *>(S->Z), S->Cfwd, S->ord_fwd);
+      irk::kern::accumulate_solution<double>(static_cast<double *>(S->Z), S->sN, S->y, 1, S->sN,
+                                             z_dev, S->stream);
+    }
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return IRK_OK;
+  });
+}
+
+void irk_destroy(irk_solver *S) {
+  if (!S) return;
+  (void)hipStreamSynchronize(S->stream);
+  for (const auto &t : S->prof_pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : S->prof_pool) (void)hipEventDestroy(e);
+  free_list(S->op_allocs);
+  free_list(S->ws_allocs);
+  if (S->host_resid) (void)hipHostFree(S->host_resid);
+  delete S;
+}
+
+const char *irk_status_string(irk_status st) {
+  switch (st) {
+    case IRK_OK: return "IRK_OK";
+    case IRK_E_INVALID: return "IRK_E_INVALID";
+    case IRK_E_SINGULAR_PIVOT: return "IRK_E_SINGULAR_PIVOT";
+    case IRK_E_NOT_CONVERGED: return "IRK_E_NOT_CONVERGED";
+    case IRK_E_BREAKDOWN: return "IRK_E_BREAKDOWN";
+    case IRK_E_NONFINITE: return "IRK_E_NONFINITE";
+    case IRK_E_HIP: return "IRK_E_HIP";
+    case IRK_E_OOM: return "IRK_E_OOM";
+  }
+  return "unknown irk_status";
+}
+
+const char *irk_last_error(const irk_solver *S) {
+  return S ? S->err.c_str() : g_setup_error.c_str();
+}
+
+irk_status irk_profile_select(irk_solver *S, int kc) {
+  if (!S || kc < -1 || kc >= IRK_KC_COUNT) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    prof_collect(S);
+    S->prof_sel = kc;
+    S->prof_launches = 0;
+    S->prof_ms = 0.0;
+    S->prof_bytes = 0.0;
+    return IRK_OK;
+  });
+}
+
+irk_status irk_profile_read(const irk_solver *S, long long *launches, double *total_ms,
+                            double *total_bytes) {
+  if (!S) return IRK_E_INVALID;
+  if (launches) *launches = S->prof_launches;
+  if (total_ms) *total_ms = S->prof_ms;
+  if (total_bytes) *total_bytes = S->prof_bytes;
+  return IRK_OK;
+}
+
+irk_status irk_info(const irk_solver *S, int *N, int *s, int *levels, int *constant_coeff) {
+  if (!S) return IRK_E_INVALID;
+  if (N) *N = (int)S->N;
+  if (s) *s = S->s;
+  if (levels) *levels = S->nlev;
+  if (constant_coeff) *constant_coeff = S->const_mode ? 1 : 0;
+  return IRK_OK;
+}
+
+}  // extern "C"
