@@ -92,11 +92,16 @@ typedef struct {
   int precond;     /* IRK_PREC_LD (the paper's method), DU, GSL or J */
   int restart;     /* FGMRES restart length m (1..200) */
   int max_iter;    /* total Krylov iterations allowed per solve */
-  int nu_pre;      /* red-black Gauss-Seidel sweeps before the coarse correction */
-  int nu_post;     /* sweeps after it */
+  int nu_pre;      /* red-black Gauss-Seidel sweeps before the coarse correction (1..3) */
+  int nu_post;     /* sweeps after it (must equal nu_pre) */
   int coarse_max;  /* coarsen while the level has more unknowns than this */
   int vcycles;     /* V-cycles per diagonal-block subsolve (the paper uses 1) */
-  int true_resid;  /* 1: recompute ||rhs - A k|| / ||rhs|| in double at exit */
+  int true_resid;  /* 1: when the estimate reports convergence, recompute
+                      ||rhs - A k|| / ||rhs|| in double and restart if it is
+                      above rtol (guards single-pass Gram-Schmidt) */
+  int reorth;      /* second classical Gram-Schmidt pass: 0 never, 1 always,
+                      2 when the first pass leaves less than 1/sqrt(2) of the
+                      vector's norm (DGKS criterion, decided on the GPU) */
   double rtol;     /* stop when the residual estimate <= rtol * ||rhs|| */
 } irk_options;
 
@@ -109,8 +114,8 @@ typedef struct {
 } irk_stats;
 
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
- * max_iter 200, nu_pre = nu_post = 2, coarse_max 256, vcycles 1,
- * true_resid 0, rtol 1e-8. */
+ * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
+ * true_resid 1, reorth 0, rtol 1e-8. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.
@@ -203,10 +208,10 @@ enum {
   IRK_KC_VEC_DOTS = 2,    /* second Gram-Schmidt pass: dots */
   IRK_KC_VEC_UPDATE = 3,  /* second Gram-Schmidt pass: update */
   IRK_KC_COUPLE = 4,      /* block-substitution coupling of one stage */
-  IRK_KC_SMOOTH_L0 = 5,   /* smoother on the finest level */
-  IRK_KC_RESTRICT_L0 = 6, /* residual + restriction from the finest level */
-  IRK_KC_PROLONG_L0 = 7,  /* prolongation + correction onto the finest level */
-  IRK_KC_COARSE = 8,      /* every V-cycle kernel on levels >= 1 */
+  IRK_KC_VDOWN_L0 = 5,    /* finest level: pre-smoothing + residual + restriction */
+  IRK_KC_VUP_L0 = 6,      /* finest level: correction + post-smoothing */
+  IRK_KC_VMID = 7,        /* both passes on the intermediate levels */
+  IRK_KC_VTAIL = 8,       /* the coarse levels solved in one workgroup */
   IRK_KC_COUNT = 9
 };
 

@@ -17,8 +17,8 @@ IRK_E_NONFINITE = -5
 IRK_E_HIP = -6
 IRK_E_OOM = -7
 
-KERNEL_CLASSES = ["spmm_dots", "spmm_update", "vec_dots", "vec_update", "couple", "smooth_l0",
-                  "restrict_l0", "prolong_l0", "coarse"]
+KERNEL_CLASSES = ["spmm_dots", "spmm_update", "vec_dots", "vec_update", "couple", "vdown_l0",
+                  "vup_l0", "vmid", "vtail"]
 
 IRK_FP64 = 0
 IRK_MIXED = 1
@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("precond", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("coarse_max", ctypes.c_int), ("vcycles", ctypes.c_int),
-                ("true_resid", ctypes.c_int), ("rtol", ctypes.c_double)]
+                ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

@@ -171,86 +171,6 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// V-cycle pieces
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_rb_sweep(OpView<T> D, T *__restrict__ x, const T *__restrict__ b, int color, int ncolors,
-               int zero_init) {
-  const size_t N = (size_t)D.nx * D.ny;
-  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= N) return;
-  const int i = (int)(p % D.nx), j = (int)(p / D.nx);
-  const int c = (ncolors == 2) ? ((i + j) & 1) : ((i & 1) + 2 * (j & 1));
-  if (c != color) {
-    if (zero_init) x[p] = T(0);
-    return;
-  }
-  T d;
-  T off = T(0);
-  if (zero_init) {
-    d = coef(D, node_class_d(i, j, D.nx, D.ny), 4, p, N);
-  } else {
-    off = offdiag_apply(D, x, i, j, p, N, d);
-  }
-  x[p] = (b[p] - off) / d;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_resid_restrict(OpView<T> D, const T *__restrict__ x, const T *__restrict__ b,
-                     T *__restrict__ rc) {
-  const int ncx = D.nx / 2, ncy = D.ny / 2;
-  const size_t Nc = (size_t)ncx * ncy;
-  const size_t N = (size_t)D.nx * D.ny;
-  const size_t I = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (I >= Nc) return;
-  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
-  T acc = T(0);
-#pragma unroll
-  for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int i = 2 * Ix + a, j = 2 * Iy + bb;
-      const size_t p = (size_t)j * D.nx + i;
-      T d;
-      const T off = offdiag_apply(D, x, i, j, p, N, d);
-      acc += b[p] - off - d * x[p];
-    }
-  rc[I] = acc;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_prolong_add(int nx, int ny, const T *__restrict__ ec, T *__restrict__ x) {
-  const size_t N = (size_t)nx * ny;
-  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= N) return;
-  const int fx = (int)(p % nx), fy = (int)(p / nx);
-  const int ncx = nx / 2, ncy = ny / 2;
-  const int Ix = fx / 2, Iy = fy / 2;
-  const int nbx = (fx & 1) ? Ix + 1 : Ix - 1;
-  const int nby = (fy & 1) ? Iy + 1 : Iy - 1;
-  const bool hx = nbx >= 0 && nbx < ncx, hy = nby >= 0 && nby < ncy;
-  T v = T(0.5625) * ec[(size_t)Iy * ncx + Ix];
-  if (hx) v += T(0.1875) * ec[(size_t)Iy * ncx + nbx];
-  if (hy) v += T(0.1875) * ec[(size_t)nby * ncx + Ix];
-  if (hx && hy) v += T(0.0625) * ec[(size_t)nby * ncx + nbx];
-  x[p] += v;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_dense_solve(const T *__restrict__ Cinv, int n, const T *__restrict__ b, T *__restrict__ x) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= n) return;
-  const T *row = Cinv + (size_t)r * n;
-  T acc = T(0);
-  for (int c = 0; c < n; ++c) acc += row[c] * b[c];
-  x[r] = acc;
-}
-
-// ---------------------------------------------------------------------------
 // Kronecker SpMM with fused Gram-Schmidt
 
 // w_i(p) = z_i(p) + sum_k hA[i][k] (K z_k)(p) for all s stages at node p.
@@ -307,6 +227,14 @@ __global__ void __launch_bounds__(kBlock)
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[(size_t)m * nblk + blockIdx.x] = t;
   }
+  // ||w||^2 as column j+1: lets the device decide on a second Gram-Schmidt pass
+  double ww = 0.0;
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < S; ++r) ww += w[r] * w[r];
+  }
+  const double t = block_sum(ww);
+  if (threadIdx.x == 0) partial[(size_t)(jj + 1) * nblk + blockIdx.x] = t;
 }
 
 template <typename TZ, int S>
@@ -346,6 +274,7 @@ constexpr int kEPT = 4;
 __global__ void __launch_bounds__(kBlock)
     k_vec_dots(const double *__restrict__ V, size_t n, const double *__restrict__ scale,
                const KrylovState *__restrict__ ks, double *__restrict__ partial) {
+  if (ks->skip_reorth) return;  // uniform over the grid
   const int jj = ks->j;
   const double *vin = V + (size_t)(jj + 1) * n;
   const size_t e0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * kEPT;
@@ -369,6 +298,7 @@ __global__ void __launch_bounds__(kBlock)
     k_vec_update(double *__restrict__ V, size_t n, const double *__restrict__ scale,
                  const double *__restrict__ h2, const KrylovState *__restrict__ ks,
                  double *__restrict__ partial) {
+  if (ks->skip_reorth) return;
   const int jj = ks->j;
   double *vin = V + (size_t)(jj + 1) * n;
   const size_t e0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * kEPT;
@@ -395,9 +325,10 @@ __global__ void __launch_bounds__(kBlock)
 
 __global__ void __launch_bounds__(kBlock)
     k_reduce_cols(const double *__restrict__ partial, int nblk,
-                  const KrylovState *__restrict__ ks, double *__restrict__ out) {
+                  const KrylovState *__restrict__ ks, int extra, int honor_skip,
+                  double *__restrict__ out) {
   const int m = blockIdx.x;
-  if (m > ks->j) return;  // uniform per block
+  if (m > ks->j + extra || (honor_skip && ks->skip_reorth)) return;  // uniform per block
   double acc = 0.0;
   const double *col = partial + (size_t)m * nblk;
   for (int b = threadIdx.x; b < nblk; b += kBlock) acc += col[b];
@@ -405,22 +336,43 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) out[m] = t;
 }
 
+// Decide on the second Gram-Schmidt pass (DGKS criterion): mode 0 never,
+// 1 always, 2 when the first pass removed more than half of ||w||^2, i.e.
+// ||v|| < ||w|| / sqrt(2).  Also keeps ||v||^2 of the first pass.
+__global__ void __launch_bounds__(kBlock)
+    k_reorth_decide(const double *__restrict__ partial_norm, int nblk,
+                    const double *__restrict__ h1, KrylovState *__restrict__ ks, int mode,
+                    double *__restrict__ norm_sq) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial_norm[b];
+  const double nrm2 = block_sum(acc);
+  if (threadIdx.x != 0) return;
+  const double ww = h1[ks->j + 1];
+  const bool skip = (mode == 0) || (mode == 2 && nrm2 > 0.5 * ww);
+  ks->skip_reorth = skip ? 1 : 0;
+  norm_sq[0] = nrm2;
+}
+
 // Hessenberg column j: H[:, j] = h1 (+ h2), H[j+1, j] = ||v_{j+1}||, rotate
 // with the stored Givens rotations, form the new one, update g and the
 // residual estimate |g_{j+1}|, set the lazy scale of V_{j+1}, advance j.
 __global__ void __launch_bounds__(kBlock)
     k_givens(const double *__restrict__ h1, const double *__restrict__ h2,
-             const double *__restrict__ partial_norm, int nblk, double *__restrict__ H, int ldh,
+             const double *__restrict__ partial_norm, int nblk,
+             const double *__restrict__ norm_sq_first, double *__restrict__ H, int ldh,
              double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
              double *__restrict__ scale, KrylovState *__restrict__ ks, double beta, double rtol,
              double *__restrict__ host_resid) {
+  const bool second = !ks->skip_reorth;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial_norm[b];
-  const double nrm2 = block_sum(acc);
+  if (second)
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial_norm[b];
+  const double nrm2s = block_sum(acc);
   if (threadIdx.x != 0) return;
+  const double nrm2 = second ? nrm2s : norm_sq_first[0];
   const int j = ks->j;
   double *Hc = H + (size_t)j * ldh;
-  for (int m = 0; m <= j; ++m) Hc[m] = h1[m] + (h2 ? h2[m] : 0.0);
+  for (int m = 0; m <= j; ++m) Hc[m] = h1[m] + (second ? h2[m] : 0.0);
   const double nrm = sqrt(nrm2);
   Hc[j + 1] = nrm;
   for (int m = 0; m < j; ++m) {
@@ -657,29 +609,6 @@ void couple(const OpView<T> &K, const double *v, const double *scale_j, const T 
   k_couple<T><<<nblocks(N), kBlock, 0, st>>>(K, v, scale_j, z, pack_row(C, s), s, i, b);
 }
 
-template <typename T>
-void rb_sweep(const OpView<T> &D, T *x, const T *b, int color, int zero_init, hipStream_t st) {
-  const size_t N = (size_t)D.nx * D.ny;
-  const int ncolors = (D.npt == 5) ? 2 : 4;
-  k_rb_sweep<T><<<nblocks(N), kBlock, 0, st>>>(D, x, b, color, ncolors, zero_init);
-}
-
-template <typename T>
-void resid_restrict(const OpView<T> &D, const T *x, const T *b, T *rc, hipStream_t st) {
-  const size_t Nc = (size_t)(D.nx / 2) * (D.ny / 2);
-  k_resid_restrict<T><<<nblocks(Nc), kBlock, 0, st>>>(D, x, b, rc);
-}
-
-template <typename T>
-void prolong_add(int nx, int ny, const T *ec, T *x, hipStream_t st) {
-  k_prolong_add<T><<<nblocks((size_t)nx * ny), kBlock, 0, st>>>(nx, ny, ec, x);
-}
-
-template <typename T>
-void dense_solve(const T *Cinv, int n, const T *b, T *x, hipStream_t st) {
-  k_dense_solve<T><<<nblocks(n), kBlock, 0, st>>>(Cinv, n, b, x);
-}
-
 #define IRK_DISPATCH_S(s, KERNEL, ...)                     \
   switch (s) {                                             \
     case 1: KERNEL(1, __VA_ARGS__); break;                 \
@@ -731,16 +660,22 @@ void vec_update(double *vin, size_t n, const double *V, const double *scale, con
                                                                      scale, h2, ks, partial);
 }
 
-void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, double *out,
-                 hipStream_t st) {
-  k_reduce_cols<<<jmax + 1, kBlock, 0, st>>>(partial, nblk, ks, out);
+void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, int extra,
+                 int honor_skip, double *out, hipStream_t st) {
+  k_reduce_cols<<<jmax + 1 + extra, kBlock, 0, st>>>(partial, nblk, ks, extra, honor_skip, out);
 }
 
-void givens(const double *h1, const double *h2, const double *partial_norm, int nblk, double *H,
-            int ldh, double *cs, double *sn, double *g, double *scale, KrylovState *ks,
-            double beta, double rtol, double *host_resid, hipStream_t st) {
-  k_givens<<<1, kBlock, 0, st>>>(h1, h2, partial_norm, nblk, H, ldh, cs, sn, g, scale, ks, beta,
-                                 rtol, host_resid);
+void reorth_decide(const double *partial_norm, int nblk, const double *h1, KrylovState *ks,
+                   int mode, double *norm_sq, hipStream_t st) {
+  k_reorth_decide<<<1, kBlock, 0, st>>>(partial_norm, nblk, h1, ks, mode, norm_sq);
+}
+
+void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
+            const double *norm_sq_first, double *H, int ldh, double *cs, double *sn, double *g,
+            double *scale, KrylovState *ks, double beta, double rtol, double *host_resid,
+            hipStream_t st) {
+  k_givens<<<1, kBlock, 0, st>>>(h1, h2, partial_norm, nblk, norm_sq_first, H, ldh, cs, sn, g,
+                                 scale, ks, beta, rtol, host_resid);
 }
 
 void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st) {
@@ -809,17 +744,6 @@ template void couple<float>(const OpView<float> &, const double *, const double 
                             const double *, int, int, float *, hipStream_t);
 template void couple<double>(const OpView<double> &, const double *, const double *,
                              const double *, const double *, int, int, double *, hipStream_t);
-template void rb_sweep<float>(const OpView<float> &, float *, const float *, int, int, hipStream_t);
-template void rb_sweep<double>(const OpView<double> &, double *, const double *, int, int,
-                               hipStream_t);
-template void resid_restrict<float>(const OpView<float> &, const float *, const float *, float *,
-                                    hipStream_t);
-template void resid_restrict<double>(const OpView<double> &, const double *, const double *,
-                                     double *, hipStream_t);
-template void prolong_add<float>(int, int, const float *, float *, hipStream_t);
-template void prolong_add<double>(int, int, const double *, double *, hipStream_t);
-template void dense_solve<float>(const float *, int, const float *, float *, hipStream_t);
-template void dense_solve<double>(const double *, int, const double *, double *, hipStream_t);
 template void spmm_dots<float>(const OpView<double> &, const float *, const double *, int,
                                const double *, const double *, const KrylovState *, int, double *,
                                hipStream_t);

@@ -23,13 +23,30 @@ struct OpView {
   const T *arr;
 };
 
+// The coarse end of the hierarchy, solved by one workgroup in LDS: levels
+// 0..nlev-1 of the tail (level 0 = the finest tail level, at most kTailMax
+// nodes), operators of every level but the last, and the transposed dense
+// inverse of the last.
+constexpr int kTailMax = 4096;
+constexpr int kTailLevels = 8;
+constexpr int kTailMaxCoarse = 1024;  // largest dense coarsest level
+template <typename T>
+struct TailDesc {
+  int nlev;
+  int nx[kTailLevels], ny[kTailLevels];
+  size_t off[kTailLevels + 1];  // LDS offset (elements) of level l: b then x; off[nlev] = end
+  const T *cls[kTailLevels];
+  const T *arr[kTailLevels];
+  const T *CinvT;
+};
+
 // Scalars the Krylov kernels read from device memory so that a whole
 // iteration can be replayed without host arguments changing.
 struct KrylovState {
-  int j;          // current iteration (column) index within the cycle
-  int converged;  // set by the Givens kernel
-  int breakdown;  // set by the Givens kernel
-  int pad;
+  int j;            // current iteration (column) index within the cycle
+  int converged;    // set by the Givens kernel
+  int breakdown;    // set by the Givens kernel
+  int skip_reorth;  // set by the reorthogonalisation decision
 };
 
 namespace kern {
@@ -54,23 +71,25 @@ template <typename T>
 void couple(const OpView<T> &K, const double *v, const double *scale_j, const T *z,
             const double *C, int s, int i, T *b, hipStream_t st);
 
-// Red-black Gauss-Seidel half sweep on colour ((i + j) % 2 == color) of
-// D x = b.  zero_init: x was zero, so x_c = b_c / d_c and the other colour is
-// written as zero.
+// Fused V-cycle passes on one level (vcycle.hip): nu red-black Gauss-Seidel
+// sweeps from zero, then rc = R (b - D x) (down); the same sweeps, x += P ec
+// and nu post-sweeps (up).  nu in 1..3.
 template <typename T>
-void rb_sweep(const OpView<T> &D, T *x, const T *b, int color, int zero_init, hipStream_t st);
-
-// rc[I] = sum over the 2x2 aggregate of (b - D x).
+void vdown(const OpView<T> &D, int nu, const T *b, T *rc, hipStream_t st);
 template <typename T>
-void resid_restrict(const OpView<T> &D, const T *x, const T *b, T *rc, hipStream_t st);
-
-// x += P ec (cell-centred bilinear interpolation from the coarse grid).
+void vup(const OpView<T> &D, int nu, const T *b, const T *ec, T *x, hipStream_t st);
+// The finest-level down pass with the stage coupling of Sec. 4.2 fused in:
+// b = scale_j v_i - K (sum_k C[k] z_k) is formed in LDS, written to b_out for
+// the up pass, smoothed and restricted.  v = V_j (double), z = Z_j (T).
 template <typename T>
-void prolong_add(int nx, int ny, const T *ec, T *x, hipStream_t st);
-
-// x = Cinv b, dense n x n (row-major), the coarsest-level solve.
+void vdown_couple(const OpView<T> &D, const OpView<T> &K, int nu, const double *v,
+                  const double *scale_j, const T *z, const double *C, int s, int i, T *b_out,
+                  T *rc, hipStream_t st);
+// The whole V-cycle below (and including) the first tail level, one workgroup.
 template <typename T>
-void dense_solve(const T *Cinv, int n, const T *b, T *x, hipStream_t st);
+size_t vtail_lds_bytes(const TailDesc<T> &td);
+template <typename T>
+void vtail(const TailDesc<T> &td, int nu, const T *b, T *x, hipStream_t st);
 
 // Kronecker SpMM with fused classical Gram-Schmidt dots:
 //   w = z + (hA (x) K) z  (M = I), z = Z_j (TZ, stage-major)
@@ -94,14 +113,21 @@ void vec_dots(const double *vin, size_t n, const double *V, const double *scale,
 void vec_update(double *vin, size_t n, const double *V, const double *scale, const double *h2,
                 const KrylovState *ks, double *partial, hipStream_t st);
 
-// out[m] = sum_b partial[m * nblk + b] for m = 0..j (one block per column).
-void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, double *out,
-                 hipStream_t st);
+// out[m] = sum_b partial[m * nblk + b] for m = 0..j+extra (one block per
+// column); with honor_skip, nothing when the second pass is skipped.
+void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, int extra,
+                 int honor_skip, double *out, hipStream_t st);
+
+// Second-pass decision (0 never, 1 always, 2 DGKS) from the first pass's
+// partial norms and ||w||^2 = h1[j+1]; stores ||v||^2 in norm_sq[0].
+void reorth_decide(const double *partial_norm, int nblk, const double *h1, KrylovState *ks,
+                   int mode, double *norm_sq, hipStream_t st);
 
 // Single-block Hessenberg/Givens step for column j (see solver).
 void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
-            double *H, int ldh, double *cs, double *sn, double *g, double *scale,
-            KrylovState *ks, double beta, double rtol, double *host_resid, hipStream_t st);
+            const double *norm_sq_first, double *H, int ldh, double *cs, double *sn, double *g,
+            double *scale, KrylovState *ks, double beta, double rtol, double *host_resid,
+            hipStream_t st);
 
 // Back substitution H y = g for the leading k x k block, single block.
 void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);

@@ -63,6 +63,7 @@ struct irk_solver {
   irk_options opt{};
   bool const_mode = false, symmetric = false;
   int nlev = 0, ncoarse = 0;
+  int lt = 0;  // first level handled by the single-workgroup tail kernel
   std::vector<int> lnx, lny;
 
   // operators (rebuilt by irk_update_operator)
@@ -77,7 +78,7 @@ struct irk_solver {
   // workspace
   double *V = nullptr, *acc = nullptr, *f = nullptr, *g = nullptr, *rhs = nullptr;
   double *Ubuf = nullptr, *zero = nullptr, *gbuf = nullptr;
-  double *partial = nullptr, *pnorm = nullptr;
+  double *partial = nullptr, *pnorm = nullptr, *pnorm2 = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *y = nullptr;
   double *scale = nullptr, *h1 = nullptr, *h2 = nullptr, *norm_dev = nullptr;
   double *dev_resid = nullptr;
@@ -223,7 +224,7 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   }
   const int L = (int)Sl.size();
   const long long ncoarse = (long long)Sl.back().nx * Sl.back().ny;
-  if (ncoarse > 1024) {
+  if (ncoarse > irk::kTailMaxCoarse) {
     S->err = "the grid does not coarsen to at most 1024 unknowns by halving (nx, ny must stay "
              "even down to coarse_max)";
     return IRK_E_INVALID;
@@ -239,6 +240,20 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   for (int l = 0; l < L; ++l) {
     S->lnx.push_back(Sl[l].nx);
     S->lny.push_back(Sl[l].ny);
+  }
+  // the tail starts at the first level that fits one workgroup's LDS (<= 64 KiB)
+  {
+    const size_t es = (S->opt.precision == IRK_MIXED) ? 4 : 8;
+    S->lt = L - 1;
+    for (int l = 0; l < L; ++l) {
+      size_t words = 1024 + 81 * (size_t)(L - l);  // reduction buffer + class tables
+      for (int m = l; m < L; ++m) words += 2 * (size_t)Sl[m].nx * Sl[m].ny;
+      if ((size_t)Sl[l].nx * Sl[l].ny <= (size_t)irk::kTailMax && words * es <= 65536 &&
+          L - l <= irk::kTailLevels) {
+        S->lt = l;
+        break;
+      }
+    }
   }
   free_list(S->op_allocs);
   S->D64.assign(S->s, {});
@@ -264,7 +279,11 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
       S->err = "singular coarsest-level block";
       return IRK_E_INVALID;
     }
+    // stored transposed: the tail kernel reads column c of the inverse contiguously
     const size_t nn = inv.size();
+    const size_t nc = (size_t)ncoarse;
+    for (size_t r = 0; r < nc; ++r)
+      for (size_t c = r + 1; c < nc; ++c) std::swap(inv[r * nc + c], inv[c * nc + r]);
     if (mixed) {
       std::vector<float> hf(inv.begin(), inv.end());
       S->Cinv32[i] = dalloc<float>(S->op_allocs, nn);
@@ -297,6 +316,7 @@ void alloc_workspace(irk_solver *S) {
                              (size_t)((S->nx + 2) * (size_t)(S->ny + 2) / irk::kBlock + 2)});
   S->partial = dalloc<double>(L, S->partial_len);
   S->pnorm = dalloc<double>(L, std::max({nblk_pt, nblk_vec, nblk_full}));
+  S->pnorm2 = dalloc<double>(L, std::max({nblk_pt, nblk_vec, nblk_full}));
   S->H = dalloc<double>(L, (size_t)(m + 1) * m);
   S->cs = dalloc<double>(L, m + 1);
   S->sn = dalloc<double>(L, m + 1);
@@ -354,55 +374,66 @@ OpView<float> Kview<float>(const irk_solver *S) {
   return S->K32.view();
 }
 
-// One V-cycle for the stage-i block on level l: x ~= D_il^-1 b (x is overwritten).
 template <typename T>
-void vcycle(irk_solver *S, int i, int l, const T *b, T *x) {
+T *lev_b(irk_solver *S, int l) {
+  return static_cast<T *>(S->levb) + S->lev_off[l];
+}
+template <typename T>
+T *lev_x(irk_solver *S, int l) {
+  return static_cast<T *>(S->levx) + S->lev_off[l];
+}
+
+// One V(nu, nu)-cycle for the stage-i block, x ~= D_i^-1 b on the finest
+// level (Sec. 4.2): fused down passes to the tail level, the tail in one
+// workgroup, fused up passes back.
+template <typename T>
+void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   hipStream_t st = S->stream;
-  if (l == S->nlev - 1) {
-    ProfTok t = prof_begin(S, IRK_KC_COARSE,
-                           (double)S->ncoarse * (S->ncoarse + 2.0) * sizeof(T));
-    irk::kern::dense_solve<T>(Cinv<T>(S, i), S->ncoarse, b, x, st);
+  const int nu = S->opt.nu_pre, lt = S->lt, L = S->nlev;
+  const size_t es = sizeof(T);
+  auto bl = [&](int l) -> const T * { return l == 0 ? b : lev_b<T>(S, l); };
+  auto xl = [&](int l) -> T * { return l == 0 ? x : lev_x<T>(S, l); };
+  for (int l = finest_down_done ? 1 : 0; l < lt; ++l) {
+    const DevOp<T> &D = Dops<T>(S)[i][l];
+    const size_t n = (size_t)D.nx * D.ny;
+    ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID,
+                           (double)n * es * 1.25 + op_bytes(S, n, D.npt, es));
+    irk::kern::vdown<T>(D.view(), nu, bl(l), lev_b<T>(S, l + 1), st);
     prof_end(S, t);
-    return;
   }
-  const DevOp<T> &D = Dops<T>(S)[i][l];
-  const OpView<T> v = D.view();
-  const int nc = (D.npt == 5) ? 2 : 4;
-  const size_t n = (size_t)D.nx * D.ny, es = sizeof(T);
-  const int kc_s = (l == 0) ? IRK_KC_SMOOTH_L0 : IRK_KC_COARSE;
-  const int kc_r = (l == 0) ? IRK_KC_RESTRICT_L0 : IRK_KC_COARSE;
-  const int kc_p = (l == 0) ? IRK_KC_PROLONG_L0 : IRK_KC_COARSE;
-  const double cb = op_bytes(S, n, D.npt, es);
-  if (S->opt.nu_pre <= 0) HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(T), st));
-  for (int sw = 0; sw < S->opt.nu_pre; ++sw)
-    for (int c = 0; c < nc; ++c) {
-      const bool z0 = (sw == 0 && c == 0);
-      // one colour: read b and the neighbours of that colour's nodes, write it
-      // (a zero start reads b of the colour and writes every node)
-      ProfTok t = prof_begin(S, kc_s, z0 ? (double)n * es * (1.0 / nc + 1.0)
-                                         : (double)n * es * (1.0 + 2.0 / nc) + cb / nc);
-      irk::kern::rb_sweep<T>(v, x, b, c, z0 ? 1 : 0, st);
-      prof_end(S, t);
-    }
-  T *bc = static_cast<T *>(S->levb) + S->lev_off[l + 1];
-  T *xc = static_cast<T *>(S->levx) + S->lev_off[l + 1];
   {
-    ProfTok t = prof_begin(S, kc_r, (double)n * es * 2.25 + cb);
-    irk::kern::resid_restrict<T>(v, x, b, bc, st);
-    prof_end(S, t);
-  }
-  vcycle<T>(S, i, l + 1, bc, xc);
-  {
-    ProfTok t = prof_begin(S, kc_p, (double)n * es * 2.25);
-    irk::kern::prolong_add<T>(D.nx, D.ny, xc, x, st);
-    prof_end(S, t);
-  }
-  for (int sw = 0; sw < S->opt.nu_post; ++sw)
-    for (int c = nc - 1; c >= 0; --c) {
-      ProfTok t = prof_begin(S, kc_s, (double)n * es * (1.0 + 2.0 / nc) + cb / nc);
-      irk::kern::rb_sweep<T>(v, x, b, c, 0, st);
-      prof_end(S, t);
+    irk::TailDesc<T> td{};
+    td.nlev = L - lt;
+    size_t off = 0, words = 0;
+    for (int k = 0; k < td.nlev; ++k) {
+      const int l = lt + k;
+      td.nx[k] = S->lnx[l];
+      td.ny[k] = S->lny[l];
+      td.off[k] = off;
+      off += 2 * (size_t)S->lnx[l] * S->lny[l];
+      if (l < L - 1) {
+        const DevOp<T> &D = Dops<T>(S)[i][l];
+        td.cls[k] = D.cls;
+        td.arr[k] = D.arr;
+        if (D.arr) words += 9 * (size_t)D.nx * D.ny;
+      }
     }
+    td.off[td.nlev] = off;
+    td.CinvT = Cinv<T>(S, i);
+    const size_t ntop = (size_t)S->lnx[lt] * S->lny[lt];
+    words += 2 * ntop + (size_t)S->ncoarse * S->ncoarse;
+    ProfTok t = prof_begin(S, IRK_KC_VTAIL, (double)words * es);
+    irk::kern::vtail<T>(td, nu, bl(lt), xl(lt), st);
+    prof_end(S, t);
+  }
+  for (int l = lt - 1; l >= 0; --l) {
+    const DevOp<T> &D = Dops<T>(S)[i][l];
+    const size_t n = (size_t)D.nx * D.ny;
+    ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID,
+                           (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
+    irk::kern::vup<T>(D.view(), nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
+    prof_end(S, t);
+  }
 }
 
 // z = P^-1 v by block substitution (Sec. 4.2).  v = V_j (lazy scale
@@ -411,17 +442,30 @@ template <typename T>
 void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, const double *C,
                    const int *ord) {
   T *b0 = static_cast<T *>(S->b0);
+  const size_t N = S->N, es = sizeof(T);
   for (int t = 0; t < S->s; ++t) {
     const int i = ord[t];
     int ncoup = 0;
     for (int k = 0; k < S->s; ++k) ncoup += (C[(size_t)i * S->s + k] != 0.0);
-    // v_i (double), the coupled z_k and the output b
-    ProfTok tk = prof_begin(S, IRK_KC_COUPLE,
-                            (double)S->N * (8.0 + sizeof(T) * (ncoup + 1)) +
-                                (ncoup ? op_bytes(S, S->N, S->K64.npt, sizeof(T)) : 0.0));
-    irk::kern::couple<T>(Kview<T>(S), v, scale_j, z, C + (size_t)i * S->s, S->s, i, b0, S->stream);
-    prof_end(S, tk);
-    vcycle<T>(S, i, 0, b0, z + (size_t)i * S->N);
+    // v_i (double), the coupled z_k and the right-hand side b
+    const double cbytes = (double)N * (8.0 + es * (ncoup + 1)) +
+                          (ncoup ? op_bytes(S, N, S->K64.npt, es) : 0.0);
+    if (S->lt > 0) {
+      // coupling fused into the finest-level down pass (+ rc = R(b - D x))
+      const DevOp<T> &D = Dops<T>(S)[i][0];
+      ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,
+                              cbytes + (double)N * es * 0.25 + op_bytes(S, N, D.npt, es));
+      irk::kern::vdown_couple<T>(D.view(), Kview<T>(S), S->opt.nu_pre, v, scale_j, z,
+                                 C + (size_t)i * S->s, S->s, i, b0, lev_b<T>(S, 1), S->stream);
+      prof_end(S, tk);
+      vcycle<T>(S, i, b0, z + (size_t)i * N, true);
+    } else {
+      ProfTok tk = prof_begin(S, IRK_KC_COUPLE, cbytes);
+      irk::kern::couple<T>(Kview<T>(S), v, scale_j, z, C + (size_t)i * S->s, S->s, i, b0,
+                           S->stream);
+      prof_end(S, tk);
+      vcycle<T>(S, i, b0, z + (size_t)i * N, false);
+    }
   }
 }
 
@@ -473,7 +517,7 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
   double beta = beta0;
   int total = 0, restarts = 0;
   irk_status status = IRK_E_NOT_CONVERGED;
-  double est = 1.0;
+  double est = 1.0, true_rel = -1.0;
   while (true) {
     KrylovState ks0{0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(S->ks, &ks0, sizeof ks0, hipMemcpyHostToDevice, st));
@@ -489,24 +533,24 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb);
       spmm_dots<T>(K, Z, sys.hA, s, S->V, S->scale, S->ks, j, S->partial, st);
       prof_end(S, t1);
-      reduce_cols(S->partial, nblk_pt, S->ks, j, S->h1, st);
+      reduce_cols(S->partial, nblk_pt, S->ks, j, 1, 0, S->h1, st);
       ProfTok t2 = prof_begin(S, IRK_KC_SPMM_UPDATE, zb + vb * (j + 2) + kb);
       spmm_update<T>(K, Z, sys.hA, s, S->V, S->scale, S->h1, S->ks, S->V, S->pnorm, st);
       prof_end(S, t2);
-      int nblk_norm = nblk_pt;
-      const double *h2 = nullptr;
-      // second classical Gram-Schmidt pass (CGS2) for a well-conditioned basis
-      ProfTok t3 = prof_begin(S, IRK_KC_VEC_DOTS, vb * (j + 2));
-      vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
-      prof_end(S, t3);
-      reduce_cols(S->partial, nblk_vec, S->ks, j, S->h2, st);
-      ProfTok t4 = prof_begin(S, IRK_KC_VEC_UPDATE, vb * (j + 3));
-      vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm, st);
-      prof_end(S, t4);
-      nblk_norm = nblk_vec;
-      h2 = S->h2;
-      givens(S->h1, h2, S->pnorm, nblk_norm, S->H, m + 1, S->cs, S->sn, S->gv, S->scale, S->ks,
-             beta0, S->opt.rtol, S->dev_resid, st);
+      // second classical Gram-Schmidt pass, skipped on the device when the
+      // first one kept most of ||w|| (reorth = 2) or never run (reorth = 0)
+      reorth_decide(S->pnorm, nblk_pt, S->h1, S->ks, S->opt.reorth, S->norm_dev + 1, st);
+      if (S->opt.reorth != 0) {
+        ProfTok t3 = prof_begin(S, IRK_KC_VEC_DOTS, vb * (j + 2));
+        vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
+        prof_end(S, t3);
+        reduce_cols(S->partial, nblk_vec, S->ks, j, 0, 1, S->h2, st);
+        ProfTok t4 = prof_begin(S, IRK_KC_VEC_UPDATE, vb * (j + 3));
+        vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm2, st);
+        prof_end(S, t4);
+      }
+      givens(S->h1, S->h2, S->pnorm2, nblk_vec, S->norm_dev + 1, S->H, m + 1, S->cs, S->sn,
+             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, st);
       HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
                              hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -539,31 +583,39 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     if (status == IRK_E_BREAKDOWN) --j;
     solve_upper(S->H, m + 1, S->gv, j, S->y, st);
     accumulate_solution<T>(Z, sN, S->y, j, sN, S->acc, st);
-    if (stop) break;
-    // restart from the true residual
-    ++restarts;
-    residual_full(K, S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V, S->partial, st);
+    if (status == IRK_E_BREAKDOWN || (stop && status == IRK_E_NOT_CONVERGED)) break;
+    if (status == IRK_OK && !S->opt.true_resid) break;  // trust the estimate
+    // true residual of the accumulated solution: verifies a converged estimate
+    // (single-pass Gram-Schmidt can make the estimate optimistic) or starts
+    // the next restart cycle
+    residual_full(K, S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V, S->partial,
+                  st);
     finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
     HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     beta = S->host_resid[0];
-    est = beta / beta0;
-    if (!(beta > S->opt.rtol * beta0)) {
-      status = std::isfinite(beta) ? IRK_OK : IRK_E_NONFINITE;
+    true_rel = beta / beta0;
+    if (!std::isfinite(beta)) {
+      status = IRK_E_NONFINITE;
+      S->err = "non-finite residual";
       break;
     }
+    if (beta <= S->opt.rtol * beta0) {
+      status = IRK_OK;
+      break;
+    }
+    if (total >= S->opt.max_iter) {
+      status = IRK_E_NOT_CONVERGED;
+      break;
+    }
+    status = IRK_E_NOT_CONVERGED;
+    ++restarts;
   }
   if (stats) {
     stats->iters = total;
     stats->restarts = restarts;
     stats->rel_resid_est = est;
-  }
-  if (S->opt.true_resid && stats) {
-    residual_full(K, S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V, S->partial, st);
-    finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
-    HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    stats->rel_resid_true = S->host_resid[0] / beta0;
+    stats->rel_resid_true = true_rel;
   }
   return status;
 }
@@ -583,11 +635,12 @@ bool valid_options(const irk_options &o, std::string &err) {
   if (o.precond < IRK_PREC_LD || o.precond > IRK_PREC_J) return err = "bad precond", false;
   if (o.restart < 1 || o.restart > 200) return err = "restart must be in 1..200", false;
   if (o.max_iter < 1) return err = "max_iter must be >= 1", false;
-  if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre > 8 || o.nu_post > 8)
-    return err = "nu_pre/nu_post must be in 0..8", false;
+  if (o.nu_pre < 1 || o.nu_pre > 3 || o.nu_post != o.nu_pre)
+    return err = "nu_pre = nu_post in 1..3 is required", false;
   if (o.coarse_max < 1) return err = "coarse_max must be >= 1", false;
   if (o.vcycles != 1) return err = "only one V-cycle per subsolve is implemented", false;
   if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return err = "rtol must be in (0, 1)", false;
+  if (o.reorth < 0 || o.reorth > 2) return err = "reorth must be 0, 1 or 2", false;
   return true;
 }
 
@@ -623,9 +676,10 @@ void irk_default_options(irk_options *o) {
   o->max_iter = 200;
   o->nu_pre = 2;
   o->nu_post = 2;
-  o->coarse_max = 256;
+  o->coarse_max = 64;
   o->vcycles = 1;
-  o->true_resid = 0;
+  o->true_resid = 1;
+  o->reorth = 0;
   o->rtol = 1e-8;
 }
 

@@ -40,7 +40,7 @@ def test_all_header_symbols_exported():
 def test_default_options():
     o = B.default_options()
     assert (o.precision, o.precond, o.restart, o.max_iter, o.nu_pre, o.nu_post, o.coarse_max,
-            o.vcycles, o.true_resid) == (0, 0, 40, 200, 2, 2, 256, 1, 0)
+            o.vcycles, o.true_resid, o.reorth) == (0, 0, 40, 200, 2, 2, 64, 1, 1, 0)
     assert o.rtol == 1e-8
 
 
