@@ -15,12 +15,15 @@ constexpr int kMaxStages = 8;
 //                  coefficient k of boundary class q (see node_class).
 //  arr != nullptr: per-node coefficients, arr[k * N + p].
 //  npt = 5: only the centre and the four edge neighbours are nonzero.
+//  uniform: constant coefficients whose boundary rows are the interior
+//           stencil without the couplings that leave the grid.
 template <typename T>
 struct OpView {
   int nx, ny;
   int npt;
   const T *cls;
   const T *arr;
+  int uniform;
 };
 
 // The coarse end of the hierarchy, solved by one workgroup in LDS: levels
@@ -85,6 +88,18 @@ template <typename T>
 void vdown_couple(const OpView<T> &D, const OpView<T> &K, int nu, const double *v,
                   const double *scale_j, const T *z, const double *C, int s, int i, T *b_out,
                   T *rc, hipStream_t st);
+// The same passes register-tiled per wavefront (wtile.hip): rows in
+// registers, east/west neighbours through DPP lane shifts.
+template <typename T>
+bool wtile_ok(const OpView<T> &D);
+template <typename T>
+void wdown(const OpView<T> &D, int nu, const T *b, T *rc, hipStream_t st);
+template <typename T>
+void wdown_couple(const OpView<T> &D, const OpView<T> &K, int nu, const double *v,
+                  const double *scale_j, const T *z, const double *C, int s, int i, T *b_out,
+                  T *rc, hipStream_t st);
+template <typename T>
+void wup(const OpView<T> &D, int nu, const T *b, const T *ec, T *x, hipStream_t st);
 // The whole V-cycle below (and including) the first tail level, one workgroup.
 template <typename T>
 size_t vtail_lds_bytes(const TailDesc<T> &td);

@@ -34,8 +34,22 @@ struct DevOp {
   int nx = 0, ny = 0, npt = 9;
   T *cls = nullptr;
   T *arr = nullptr;
-  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr}; }
+  int uniform = 0;
+  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform}; }
 };
+
+// A constant-coefficient operator is uniform when every boundary class equals
+// the interior stencil except for the couplings that leave the grid.
+bool classes_uniform(const double cls[9][9]) {
+  for (int q = 0; q < 9; ++q)
+    for (int k = 0; k < 9; ++k) {
+      const int cx = q % 3, cy = q / 3, dx = k % 3 - 1, dy = k / 3 - 1;
+      const bool outside =
+          (cx == 0 && dx < 0) || (cx == 2 && dx > 0) || (cy == 0 && dy < 0) || (cy == 2 && dy > 0);
+      if (!outside && std::fabs(cls[q][k] - cls[4][k]) > 1e-14 * std::fabs(cls[4][4])) return false;
+    }
+  return true;
+}
 
 struct HipError {
   hipError_t e;
@@ -177,6 +191,7 @@ DevOp<T> upload_op(irk_solver *S, const Stencil9 &op, bool use_classes, int npt)
   if (use_classes) {
     double cls[9][9];
     irk::classify(op, 1e-12, cls);
+    d.uniform = classes_uniform(cls) ? 1 : 0;
     std::vector<T> h(81);
     for (int q = 0; q < 9; ++q)
       for (int k = 0; k < 9; ++k) h[q * 9 + k] = (T)cls[q][k];
@@ -398,7 +413,10 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID,
                            (double)n * es * 1.25 + op_bytes(S, n, D.npt, es));
-    irk::kern::vdown<T>(D.view(), nu, bl(l), lev_b<T>(S, l + 1), st);
+    if (irk::kern::wtile_ok<T>(D.view()))
+      irk::kern::wdown<T>(D.view(), nu, bl(l), lev_b<T>(S, l + 1), st);
+    else
+      irk::kern::vdown<T>(D.view(), nu, bl(l), lev_b<T>(S, l + 1), st);
     prof_end(S, t);
   }
   {
@@ -431,7 +449,10 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID,
                            (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
-    irk::kern::vup<T>(D.view(), nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
+    if (irk::kern::wtile_ok<T>(D.view()))
+      irk::kern::wup<T>(D.view(), nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
+    else
+      irk::kern::vup<T>(D.view(), nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
     prof_end(S, t);
   }
 }
@@ -455,8 +476,12 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
       const DevOp<T> &D = Dops<T>(S)[i][0];
       ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,
                               cbytes + (double)N * es * 0.25 + op_bytes(S, N, D.npt, es));
-      irk::kern::vdown_couple<T>(D.view(), Kview<T>(S), S->opt.nu_pre, v, scale_j, z,
-                                 C + (size_t)i * S->s, S->s, i, b0, lev_b<T>(S, 1), S->stream);
+      if (irk::kern::wtile_ok<T>(D.view()) && irk::kern::wtile_ok<T>(Kview<T>(S)))
+        irk::kern::wdown_couple<T>(D.view(), Kview<T>(S), S->opt.nu_pre, v, scale_j, z,
+                                   C + (size_t)i * S->s, S->s, i, b0, lev_b<T>(S, 1), S->stream);
+      else
+        irk::kern::vdown_couple<T>(D.view(), Kview<T>(S), S->opt.nu_pre, v, scale_j, z,
+                                   C + (size_t)i * S->s, S->s, i, b0, lev_b<T>(S, 1), S->stream);
       prof_end(S, tk);
       vcycle<T>(S, i, b0, z + (size_t)i * N, true);
     } else {
