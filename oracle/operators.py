@@ -22,13 +22,15 @@ def _tridiag_1d(n, h):
     return sp.diags([-e[:-1], 2.0 * e, -e[:-1]], [-1, 0, 1], format="csr") / (h * h)
 
 
-def heat_K(n, length=1.0):
+def heat_K(n, length=1.0, ny=None):
     """Five-point negative Laplacian on the n x n interior grid of a square of
-    side ``length`` with homogeneous Dirichlet data: ``K = I (x) T + T (x) I``."""
+    side ``length`` with homogeneous Dirichlet data: ``K = I (x) T + T (x) I``.
+    With ``ny`` rows instead of n (same spacing ``length / (n + 1)``):
+    ``K = I_ny (x) T_n + T_ny (x) I_n``."""
+    ny = n if ny is None else ny
     h = length / (n + 1)
-    T = _tridiag_1d(n, h)
-    I = sp.identity(n, format="csr")
-    return (sp.kron(I, T) + sp.kron(T, I)).tocsr()
+    return (sp.kron(sp.identity(ny), _tridiag_1d(n, h)) +
+            sp.kron(_tridiag_1d(ny, h), sp.identity(n))).tocsr()
 
 
 def heat_eigenvalues(n, length=1.0):

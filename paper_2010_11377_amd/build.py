@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 
-HIP_SOURCES = ["host_setup.cpp", "kernels.hip", "vcycle.hip", "wtile.hip", "solver.hip"]
+HIP_SOURCES = ["host_setup.cpp", "kernels.hip", "vcycle.hip", "wtile.hip", "wsplit.hip",
+               "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,11 +26,25 @@ def _run(cmd):
     return out
 
 
+def _compile_objects(objdir):
+    """One hipcc process per source, in parallel; returns the object paths."""
+    from concurrent.futures import ThreadPoolExecutor
+    flags = [f for f in HIP_FLAGS if f != "-shared"]
+    objs = [os.path.join(objdir, os.path.splitext(src)[0] + ".o") for src in HIP_SOURCES]
+    with ThreadPoolExecutor(max_workers=min(len(HIP_SOURCES), os.cpu_count() or 1)) as ex:
+        outs = list(ex.map(lambda so: _run([HIPCC] + flags + ["-c", so[0], "-o", so[1]]),
+                           zip(HIP_SOURCES, objs)))
+    return objs, "\n".join(outs)
+
+
 def build(verbose=False):
     """Compile libirk.so (gfx950) and libirk_host_test.so (host C++ only)."""
+    import tempfile
     lib = os.path.join(HERE, "libirk.so")
     tmp = lib + ".tmp"
-    out = _run([HIPCC] + HIP_FLAGS + ["-o", tmp] + HIP_SOURCES)
+    with tempfile.TemporaryDirectory(prefix="irk_build_") as objdir:
+        objs, out = _compile_objects(objdir)
+        out += _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, lib)
     host = os.path.join(HERE, "libirk_host_test.so")
     out2 = _run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", host + ".tmp",

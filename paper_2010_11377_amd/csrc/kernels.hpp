@@ -100,6 +100,19 @@ void wdown_couple(const OpView<T> &D, const OpView<T> &K, int nu, const double *
                   T *rc, hipStream_t st);
 template <typename T>
 void wup(const OpView<T> &D, int nu, const T *b, const T *ec, T *x, hipStream_t st);
+// FP32 finest-level passes with two adjacent columns per lane (wsplit.hip):
+// every lane updates one node per row in each colour half sweep.  Uniform
+// five-point operators on grids with even nx and ny; `interior` is a host
+// copy of the interior-class coefficients (9 entries) of D, resp. K.
+bool wsplit_ok(const OpView<float> &D);
+void sdown(const OpView<float> &D, const float *interior, int nu, const float *b, float *rc,
+           hipStream_t st);
+void sdown_couple(const OpView<float> &D, const float *interior, const OpView<float> &K,
+                  const float *k_interior, int nu, const double *v, const double *scale_j,
+                  const float *z, const double *C, int s, int i, float *b_out, float *rc,
+                  hipStream_t st);
+void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
+         float *x, hipStream_t st);
 // The whole V-cycle below (and including) the first tail level, one workgroup.
 template <typename T>
 size_t vtail_lds_bytes(const TailDesc<T> &td);

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/irk.h"
@@ -35,6 +36,7 @@ struct DevOp {
   T *cls = nullptr;
   T *arr = nullptr;
   int uniform = 0;
+  T interior[9] = {};  // host copy of the interior class (constant coefficients)
   OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform}; }
 };
 
@@ -195,6 +197,7 @@ DevOp<T> upload_op(irk_solver *S, const Stencil9 &op, bool use_classes, int npt)
     std::vector<T> h(81);
     for (int q = 0; q < 9; ++q)
       for (int k = 0; k < 9; ++k) h[q * 9 + k] = (T)cls[q][k];
+    for (int k = 0; k < 9; ++k) d.interior[k] = h[4 * 9 + k];
     d.cls = dalloc<T>(S->op_allocs, 81);
     HIP_TRY(hipMemcpy(d.cls, h.data(), 81 * sizeof(T), hipMemcpyHostToDevice));
   } else {
@@ -390,12 +393,54 @@ OpView<float> Kview<float>(const irk_solver *S) {
 }
 
 template <typename T>
+const DevOp<T> &Kdev(const irk_solver *S);
+template <>
+const DevOp<double> &Kdev<double>(const irk_solver *S) {
+  return S->K64;
+}
+template <>
+const DevOp<float> &Kdev<float>(const irk_solver *S) {
+  return S->K32;
+}
+
+template <typename T>
 T *lev_b(irk_solver *S, int l) {
   return static_cast<T *>(S->levb) + S->lev_off[l];
 }
 template <typename T>
 T *lev_x(irk_solver *S, int l) {
   return static_cast<T *>(S->levx) + S->lev_off[l];
+}
+
+// Fused down / up passes of one level: two columns per lane for FP32 uniform
+// five-point operators, one column per lane for other five-point operators,
+// LDS tiles for nine-point ones.
+template <typename T>
+bool split_ok(const DevOp<T> &D) {
+  if constexpr (std::is_same_v<T, float>)
+    return irk::kern::wsplit_ok(D.view());
+  else
+    return false;
+}
+
+template <typename T>
+void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, hipStream_t st) {
+  if constexpr (std::is_same_v<T, float>)
+    if (split_ok(D)) return irk::kern::sdown(D.view(), D.interior, nu, b, rc, st);
+  if (irk::kern::wtile_ok<T>(D.view()))
+    irk::kern::wdown<T>(D.view(), nu, b, rc, st);
+  else
+    irk::kern::vdown<T>(D.view(), nu, b, rc, st);
+}
+
+template <typename T>
+void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, T *x, hipStream_t st) {
+  if constexpr (std::is_same_v<T, float>)
+    if (split_ok(D)) return irk::kern::sup(D.view(), D.interior, nu, b, ec, x, st);
+  if (irk::kern::wtile_ok<T>(D.view()))
+    irk::kern::wup<T>(D.view(), nu, b, ec, x, st);
+  else
+    irk::kern::vup<T>(D.view(), nu, b, ec, x, st);
 }
 
 // One V(nu, nu)-cycle for the stage-i block, x ~= D_i^-1 b on the finest
@@ -413,10 +458,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID,
                            (double)n * es * 1.25 + op_bytes(S, n, D.npt, es));
-    if (irk::kern::wtile_ok<T>(D.view()))
-      irk::kern::wdown<T>(D.view(), nu, bl(l), lev_b<T>(S, l + 1), st);
-    else
-      irk::kern::vdown<T>(D.view(), nu, bl(l), lev_b<T>(S, l + 1), st);
+    down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), st);
     prof_end(S, t);
   }
   {
@@ -449,12 +491,19 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID,
                            (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
-    if (irk::kern::wtile_ok<T>(D.view()))
-      irk::kern::wup<T>(D.view(), nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
-    else
-      irk::kern::vup<T>(D.view(), nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
+    up_pass<T>(D, nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
     prof_end(S, t);
   }
+}
+
+// The coupled finest down pass with two columns per lane (FP32 only).
+template <typename T>
+void couple_split(irk_solver *S, const DevOp<T> &D, const double *v, const double *scale_j, T *z,
+                  const double *Crow, int i) {
+  if constexpr (std::is_same_v<T, float>)
+    irk::kern::sdown_couple(D.view(), D.interior, S->K32.view(), S->K32.interior, S->opt.nu_pre,
+                            v, scale_j, z, Crow, S->s, i, static_cast<float *>(S->b0),
+                            lev_b<float>(S, 1), S->stream);
 }
 
 // z = P^-1 v by block substitution (Sec. 4.2).  v = V_j (lazy scale
@@ -476,7 +525,9 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
       const DevOp<T> &D = Dops<T>(S)[i][0];
       ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,
                               cbytes + (double)N * es * 0.25 + op_bytes(S, N, D.npt, es));
-      if (irk::kern::wtile_ok<T>(D.view()) && irk::kern::wtile_ok<T>(Kview<T>(S)))
+      if (split_ok<T>(D) && split_ok<T>(Kdev<T>(S)))
+        couple_split(S, D, v, scale_j, z, C + (size_t)i * S->s, i);
+      else if (irk::kern::wtile_ok<T>(D.view()) && irk::kern::wtile_ok<T>(Kview<T>(S)))
         irk::kern::wdown_couple<T>(D.view(), Kview<T>(S), S->opt.nu_pre, v, scale_j, z,
                                    C + (size_t)i * S->s, S->s, i, b0, lev_b<T>(S, 1), S->stream);
       else

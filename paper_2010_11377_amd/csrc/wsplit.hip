@@ -1,0 +1,413 @@
+// Split-column register tiles for the finest-level V-cycle passes in FP32.
+//
+// Lane l of a wavefront holds grid columns X0 + 2l ("slot a") and X0 + 2l + 1
+// ("slot b") of R consecutive grid rows in registers; X0 and Y0 are even.
+// For the red-black colouring (i + j) mod 2 the colour of slot a in row r is
+// r mod 2 and slot b has the other one, so every lane of a half sweep updates
+// exactly one of its two columns and which one is fixed at compile time for
+// each row: no idle lanes and no per-lane colour masks.  West/east
+// neighbours across the lane pair come from the adjacent lane through DPP
+// wave shifts; north/south neighbours are registers of the same lane.  The
+// 2 x 2 restriction sums the two slots of two rows in one lane, and the
+// bilinear prolongation takes the neighbouring coarse column from the next or
+// previous lane.
+//
+// Five-point constant-coefficient operators whose boundary rows are the
+// interior stencil without the couplings that leave the grid (the heat
+// operator and the shifted operators I + tau K built from it), on grids with
+// even nx and ny.  Nodes outside the grid are held at zero.  The interior
+// coefficients travel as kernel arguments.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace irk {
+namespace {
+
+constexpr int kSW = 4;  // waves per workgroup, stacked in y
+
+__device__ __forceinline__ int s_lane() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ float s_next(float v) {  // value of lane + 1 (0 in lane 63)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float s_prev(float v) {  // value of lane - 1 (0 in lane 0)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+struct Row8s {
+  double c[8];
+};
+
+// Interior five-point coefficients: south (k=1), west (3), centre (4),
+// east (5), north (7), and 1 / centre.
+struct SOp {
+  int nx, ny;
+  float s, w, c, e, n, inv;
+};
+
+SOp make_sop(const OpView<float> &D, const float *interior) {
+  SOp o;
+  o.nx = D.nx;
+  o.ny = D.ny;
+  o.s = interior[1];
+  o.w = interior[3];
+  o.c = interior[4];
+  o.e = interior[5];
+  o.n = interior[7];
+  o.inv = 1.0f / o.c;
+  return o;
+}
+
+template <int R>
+struct STile {
+  float xa[R], xb[R], ba[R], bb[R];
+};
+
+// One colour half sweep over rows [M, R-M).  BOUND: the tile reaches past the
+// grid, whose outside nodes are kept at zero.
+template <bool BOUND, int R, int M>
+__device__ __forceinline__ void s_sweep(const SOp &o, STile<R> &t, int X0, int Y0, int color) {
+  const int gxa = X0 + 2 * s_lane();
+  const bool inx = gxa >= 0 && gxa < o.nx;  // nx even: slot b is inside iff slot a is
+#pragma unroll
+  for (int r = M; r < R - M; ++r) {
+    const int gy = Y0 + r;
+    const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
+    if ((r & 1) == color) {  // slot a has colour r mod 2
+      const float v = (t.ba[r] - o.s * t.xa[r - 1] - o.n * t.xa[r + 1] - o.w * s_prev(t.xb[r]) -
+                       o.e * t.xb[r]) * o.inv;
+      t.xa[r] = in ? v : 0.0f;
+    } else {
+      const float v = (t.bb[r] - o.s * t.xb[r - 1] - o.n * t.xb[r + 1] - o.w * t.xa[r] -
+                       o.e * s_next(t.xa[r])) * o.inv;
+      t.xb[r] = in ? v : 0.0f;
+    }
+  }
+}
+
+// Pre-smoothing from x = 0: the first colour-0 half sweep is x = b / d on
+// colour 0 (zero on colour 1), then 2 nu - 1 half sweeps.  Afterwards x is
+// exact on margin 2 nu - 1.
+template <bool BOUND, int R, int NU>
+__device__ __forceinline__ void s_pre(const SOp &o, STile<R> &t, int X0, int Y0) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    // b is zero outside the grid, so this x is too
+    if ((r & 1) == 0) {
+      t.xa[r] = t.ba[r] * o.inv;
+      t.xb[r] = 0.0f;
+    } else {
+      t.xb[r] = t.bb[r] * o.inv;
+      t.xa[r] = 0.0f;
+    }
+  }
+  s_sweep<BOUND, R, 1>(o, t, X0, Y0, 1);
+  if (NU >= 2) {
+    s_sweep<BOUND, R, 2>(o, t, X0, Y0, 0);
+    s_sweep<BOUND, R, 3>(o, t, X0, Y0, 1);
+  }
+  if (NU >= 3) {
+    s_sweep<BOUND, R, 4>(o, t, X0, Y0, 0);
+    s_sweep<BOUND, R, 5>(o, t, X0, Y0, 1);
+  }
+}
+
+// Post-smoothing in the reverse colour order (colour 1 first), starting from
+// x exact on margin 2 nu - 1.
+template <bool BOUND, int R, int NU>
+__device__ __forceinline__ void s_post(const SOp &o, STile<R> &t, int X0, int Y0) {
+  constexpr int M0 = 2 * NU;
+  s_sweep<BOUND, R, M0>(o, t, X0, Y0, 1);
+  s_sweep<BOUND, R, M0 + 1>(o, t, X0, Y0, 0);
+  if (NU >= 2) {
+    s_sweep<BOUND, R, M0 + 2>(o, t, X0, Y0, 1);
+    s_sweep<BOUND, R, M0 + 3>(o, t, X0, Y0, 0);
+  }
+  if (NU >= 3) {
+    s_sweep<BOUND, R, M0 + 4>(o, t, X0, Y0, 1);
+    s_sweep<BOUND, R, M0 + 5>(o, t, X0, Y0, 0);
+  }
+}
+
+// rc = R (b - D x) with R the sum over 2 x 2 cells: coarse node (I, J) takes
+// fine columns 2I, 2I+1 of rows 2J, 2J+1, i.e. both slots of one lane in two
+// rows.  Written for output rows [H, R-H) and lanes [H/2, 64-H/2).
+template <bool BOUND, int R, int H>
+__device__ __forceinline__ void s_restrict(const SOp &o, const STile<R> &t, int X0, int Y0,
+                                           float *__restrict__ rc) {
+  const int lane = s_lane();
+  const int gxa = X0 + 2 * lane;
+  const int ncx = o.nx / 2, ncy = o.ny / 2;
+  const int I = gxa >> 1;
+  const bool inx = gxa >= 0 && gxa < o.nx;
+  const bool lane_out = lane >= H / 2 && lane < 64 - H / 2 && I < ncx;
+#pragma unroll
+  for (int r = H; r < R - H; r += 2) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int rr = r + d;
+      const float ra = t.ba[rr] - o.c * t.xa[rr] - o.s * t.xa[rr - 1] - o.n * t.xa[rr + 1] -
+                       o.w * s_prev(t.xb[rr]) - o.e * t.xb[rr];
+      const float rb = t.bb[rr] - o.c * t.xb[rr] - o.s * t.xb[rr - 1] - o.n * t.xb[rr + 1] -
+                       o.w * t.xa[rr] - o.e * s_next(t.xa[rr]);
+      // a zero node outside the grid next to a nonzero one has a nonzero
+      // residual: mask it
+      const int gy = Y0 + rr;
+      const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
+      sum += in ? ra + rb : 0.0f;
+    }
+    const int J = (Y0 + r) >> 1;
+    if (lane_out && J < ncy) rc[(size_t)J * ncx + I] = sum;
+  }
+}
+
+// Rows Y0..Y0+R-1 of a grid vector, columns X0+2l and X0+2l+1, zero outside.
+template <int R>
+__device__ __forceinline__ void s_load(const float *__restrict__ g, float (&a)[R], float (&b)[R],
+                                       int X0, int Y0, int nx, int ny) {
+  const int gx = X0 + 2 * s_lane();
+  const bool inx = gx >= 0 && gx < nx;  // nx and gx even: gx + 1 < nx too
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = Y0 + r;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const float2 *>(g + (size_t)gy * nx + gx);
+    a[r] = v.x;
+    b[r] = v.y;
+  }
+}
+
+__device__ __forceinline__ bool s_interior(int X0, int Y0, int R, int nx, int ny) {
+  return X0 >= 0 && Y0 >= 0 && X0 + 128 <= nx && Y0 + R <= ny;
+}
+
+__host__ __device__ constexpr int even_up(int h) { return (h + 1) & ~1; }
+
+// Output rows per wave (TY) and register rows (R = TY + 2H).  The down pass
+// needs x exact on margin 2 nu + 1 for its residual (one more with the
+// coupling, whose right-hand side is exact only on margin 1 in x); the up
+// pass repeats the 2 nu pre-sweeps and adds 2 nu post-sweeps.  Halos are
+// even so that the tile origin stays even.
+template <int NU, bool COUPLE>
+struct SGeomD {
+  static constexpr int H = even_up(2 * NU + (COUPLE ? 1 : 0));
+  static constexpr int TY = 32;
+  static constexpr int R = TY + 2 * H;
+  static constexpr int TXO = 128 - 2 * H;
+};
+template <int NU>
+struct SGeomU {
+  static constexpr int H = even_up(4 * NU - 1);
+  static constexpr int TY = NU == 1 ? 32 : (NU == 2 ? 24 : 16);
+  static constexpr int R = TY + 2 * H;
+  static constexpr int TXO = 128 - 2 * H;
+};
+
+template <int NU, bool COUPLE>
+__global__ void __launch_bounds__(64 * kSW)
+    k_sdown(SOp o, SOp ko, const double *__restrict__ v, const double *__restrict__ scale_j,
+            const float *__restrict__ z, Row8s crow, int s, int i, const float *__restrict__ bin,
+            float *__restrict__ b_out, float *__restrict__ rc) {
+  using G = SGeomD<NU, COUPLE>;
+  constexpr int H = G::H, TY = G::TY, R = G::R;
+  const int wave = threadIdx.x >> 6, lane = s_lane();
+  const int OX = blockIdx.x * G::TXO, OY = (blockIdx.y * kSW + wave) * TY;
+  if (OY >= o.ny) return;
+  const int X0 = OX - H, Y0 = OY - H;
+  const int gxa = X0 + 2 * lane;
+  STile<R> t;
+  if (COUPLE) {
+    // b = scale_j v_i - K c with c = sum_k C[k] z_k, c on rows Y0-1 .. Y0+R
+    const size_t N = (size_t)o.nx * o.ny;
+    const double sc = *scale_j;
+    const bool inx = gxa >= 0 && gxa < o.nx;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kMaxStages; ++k)
+      if (k < s && crow.c[k] != 0.0) any = true;
+    float ca[R + 2], cb[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+      const int gy = Y0 - 1 + r;
+      float2 acc = make_float2(0.0f, 0.0f);
+      if (any && inx && gy >= 0 && gy < o.ny) {
+        const size_t p = (size_t)gy * o.nx + gxa;
+#pragma unroll
+        for (int k = 0; k < kMaxStages; ++k)
+          if (k < s && crow.c[k] != 0.0) {
+            const float2 zz = *reinterpret_cast<const float2 *>(z + (size_t)k * N + p);
+            const float ck = (float)crow.c[k];
+            acc.x += ck * zz.x;
+            acc.y += ck * zz.y;
+          }
+      }
+      ca[r] = acc.x;
+      cb[r] = acc.y;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int gy = Y0 + r;
+      const bool in = inx && gy >= 0 && gy < o.ny;
+      double2 vv = make_double2(0.0, 0.0);
+      if (in) vv = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * o.nx + gxa);
+      float va = (float)(sc * vv.x), vb = (float)(sc * vv.y);
+      if (any && in) {
+        va -= ko.c * ca[r + 1] + ko.s * ca[r] + ko.n * ca[r + 2] + ko.w * s_prev(cb[r + 1]) +
+              ko.e * cb[r + 1];
+        vb -= ko.c * cb[r + 1] + ko.s * cb[r] + ko.n * cb[r + 2] + ko.w * ca[r + 1] +
+              ko.e * s_next(ca[r + 1]);
+      }
+      t.ba[r] = va;
+      t.bb[r] = vb;
+    }
+    // the right-hand side of the output region, for the up pass
+    if (lane >= H / 2 && lane < 64 - H / 2 && gxa < o.nx) {
+#pragma unroll
+      for (int r = H; r < R - H; ++r) {
+        const int gy = Y0 + r;
+        if (gy < o.ny)
+          *reinterpret_cast<float2 *>(b_out + (size_t)gy * o.nx + gxa) = make_float2(t.ba[r], t.bb[r]);
+      }
+    }
+  } else {
+    s_load<R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  }
+  if (s_interior(X0, Y0, R, o.nx, o.ny)) {
+    s_pre<false, R, NU>(o, t, X0, Y0);
+    s_restrict<false, R, H>(o, t, X0, Y0, rc);
+  } else {
+    s_pre<true, R, NU>(o, t, X0, Y0);
+    s_restrict<true, R, H>(o, t, X0, Y0, rc);
+  }
+}
+
+// cr[q] = coarse correction of this lane's coarse column I = X0/2 + lane in
+// coarse row Y0/2 - 1 + q (zero outside the coarse grid).
+template <bool BOUND, int R, int NU>
+__device__ __forceinline__ void s_up_body(const SOp &o, STile<R> &t, const float (&cr)[R / 2 + 3],
+                                          int X0, int Y0) {
+  s_pre<BOUND, R, NU>(o, t, X0, Y0);
+  // x += P e_c on margin 2 nu - 1: fine column 2I takes 3/4 of coarse column
+  // I and 1/4 of I-1, column 2I+1 3/4 of I and 1/4 of I+1; likewise in y
+  constexpr int M = 2 * NU - 1;
+  const int gxa = X0 + 2 * s_lane();
+  const bool inx = gxa >= 0 && gxa < o.nx;
+#pragma unroll
+  for (int r = M; r < R - M; ++r) {
+    const int gy = Y0 + r;
+    const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
+    const float cj = cr[r / 2 + 1];
+    const float cn = cr[(r & 1) ? r / 2 + 2 : r / 2];
+    const float pa = 0.5625f * cj + 0.1875f * s_prev(cj) + 0.1875f * cn + 0.0625f * s_prev(cn);
+    const float pb = 0.5625f * cj + 0.1875f * s_next(cj) + 0.1875f * cn + 0.0625f * s_next(cn);
+    t.xa[r] += in ? pa : 0.0f;
+    t.xb[r] += in ? pb : 0.0f;
+  }
+  s_post<BOUND, R, NU>(o, t, X0, Y0);
+}
+
+template <int NU>
+__global__ void __launch_bounds__(64 * kSW)
+    k_sup(SOp o, const float *__restrict__ bin, const float *__restrict__ ec,
+          float *__restrict__ xout) {
+  using G = SGeomU<NU>;
+  constexpr int H = G::H, TY = G::TY, R = G::R;
+  const int wave = threadIdx.x >> 6, lane = s_lane();
+  const int OX = blockIdx.x * G::TXO, OY = (blockIdx.y * kSW + wave) * TY;
+  if (OY >= o.ny) return;
+  const int X0 = OX - H, Y0 = OY - H;
+  const int ncx = o.nx / 2, ncy = o.ny / 2;
+  STile<R> t;
+  s_load<R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  float cr[R / 2 + 3];
+  {
+    const int I = (X0 >> 1) + lane;
+#pragma unroll
+    for (int q = 0; q < R / 2 + 3; ++q) {
+      const int J = (Y0 >> 1) - 1 + q;
+      cr[q] = (I >= 0 && I < ncx && J >= 0 && J < ncy) ? ec[(size_t)J * ncx + I] : 0.0f;
+    }
+  }
+  if (s_interior(X0, Y0, R, o.nx, o.ny))
+    s_up_body<false, R, NU>(o, t, cr, X0, Y0);
+  else
+    s_up_body<true, R, NU>(o, t, cr, X0, Y0);
+  const int gxa = X0 + 2 * lane;
+  if (lane >= H / 2 && lane < 64 - H / 2 && gxa < o.nx) {
+#pragma unroll
+    for (int r = H; r < R - H; ++r) {
+      const int gy = Y0 + r;
+      if (gy < o.ny)
+        *reinterpret_cast<float2 *>(xout + (size_t)gy * o.nx + gxa) = make_float2(t.xa[r], t.xb[r]);
+    }
+  }
+}
+
+template <int NU, bool COUPLE>
+dim3 sdown_grid(int nx, int ny) {
+  using G = SGeomD<NU, COUPLE>;
+  return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kSW - 1) / (G::TY * kSW));
+}
+template <int NU>
+dim3 sup_grid(int nx, int ny) {
+  using G = SGeomU<NU>;
+  return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kSW - 1) / (G::TY * kSW));
+}
+
+template <int NU>
+void sdown_nu(const SOp &o, const float *b, float *rc, hipStream_t st) {
+  const Row8s none{};
+  k_sdown<NU, false><<<sdown_grid<NU, false>(o.nx, o.ny), 64 * kSW, 0, st>>>(
+      o, o, nullptr, nullptr, nullptr, none, 0, 0, b, nullptr, rc);
+}
+template <int NU>
+void sdown_couple_nu(const SOp &o, const SOp &ko, const double *v, const double *scale_j,
+                     const float *z, const Row8s &crow, int s, int i, float *b_out, float *rc,
+                     hipStream_t st) {
+  k_sdown<NU, true><<<sdown_grid<NU, true>(o.nx, o.ny), 64 * kSW, 0, st>>>(
+      o, ko, v, scale_j, z, crow, s, i, nullptr, b_out, rc);
+}
+template <int NU>
+void sup_nu(const SOp &o, const float *b, const float *ec, float *x, hipStream_t st) {
+  k_sup<NU><<<sup_grid<NU>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+}
+
+}  // namespace
+
+namespace kern {
+
+bool wsplit_ok(const OpView<float> &D) {
+  return D.npt == 5 && D.uniform && D.cls && D.nx % 2 == 0 && D.ny % 2 == 0;
+}
+
+#define IRK_S_NU(FN, ...)                 \
+  do {                                    \
+    if (nu == 1) FN<1>(__VA_ARGS__);      \
+    else if (nu == 2) FN<2>(__VA_ARGS__); \
+    else FN<3>(__VA_ARGS__);              \
+  } while (0)
+
+void sdown(const OpView<float> &D, const float *interior, int nu, const float *b, float *rc,
+           hipStream_t st) {
+  IRK_S_NU(sdown_nu, make_sop(D, interior), b, rc, st);
+}
+
+void sdown_couple(const OpView<float> &D, const float *interior, const OpView<float> &K,
+                  const float *k_interior, int nu, const double *v, const double *scale_j,
+                  const float *z, const double *C, int s, int i, float *b_out, float *rc,
+                  hipStream_t st) {
+  Row8s crow{};
+  for (int k = 0; k < s; ++k) crow.c[k] = C[k];
+  IRK_S_NU(sdown_couple_nu, make_sop(D, interior), make_sop(K, k_interior), v, scale_j, z, crow,
+           s, i, b_out, rc, st);
+}
+
+void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
+         float *x, hipStream_t st) {
+  IRK_S_NU(sup_nu, make_sop(D, interior), b, ec, x, st);
+}
+
+}  // namespace kern
+}  // namespace irk

@@ -15,15 +15,16 @@ import numpy as np
 _OFFS = [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)]
 
 
-def _assemble(n, coef):
-    """CSR from five coefficient fields coef[k] (n x n, indexed [j, i]) for
+def _assemble(n, coef, ny=None):
+    """CSR from five coefficient fields coef[k] (ny x n, indexed [j, i]) for
     the neighbours in _OFFS; couplings that leave the grid are dropped."""
-    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ny = n if ny is None else ny
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(n), indexing="ij")
     present = []
     for (dx, dy) in _OFFS:
-        present.append((ii + dx >= 0) & (ii + dx < n) & (jj + dy >= 0) & (jj + dy < n))
+        present.append((ii + dx >= 0) & (ii + dx < n) & (jj + dy >= 0) & (jj + dy < ny))
     counts = np.sum(np.stack(present), axis=0).ravel()
-    indptr = np.zeros(n * n + 1, dtype=np.int64)
+    indptr = np.zeros(n * ny + 1, dtype=np.int64)
     np.cumsum(counts, out=indptr[1:])
     nnz = int(indptr[-1])
     indices = np.empty(nnz, dtype=np.int32)
@@ -39,12 +40,14 @@ def _assemble(n, coef):
     return indptr.astype(np.int32), indices, data
 
 
-def heat(n, length=1.0):
-    """Five-point ``-Laplacian``, homogeneous Dirichlet, spacing length/(n+1)."""
+def heat(n, length=1.0, ny=None):
+    """Five-point ``-Laplacian``, homogeneous Dirichlet, spacing length/(n+1)
+    in both directions, on n columns and ``ny`` (default n) rows."""
+    ny = n if ny is None else ny
     h = length / (n + 1)
     inv = 1.0 / (h * h)
-    f = np.full((n, n), -inv)
-    return _assemble(n, [f, f, np.full((n, n), 4.0 * inv), f, f])
+    f = np.full((ny, n), -inv)
+    return _assemble(n, [f, f, np.full((ny, n), 4.0 * inv), f, f], ny)
 
 
 def double_glazing(n, eps):

@@ -1,0 +1,159 @@
+"""Pins for the oracle's multigrid V-cycle (the approximate block subsolve of
+Sec. 4.2; the components are the reading stated in ``oracle/amg.py``).
+
+Independent facts used:
+* hand-derived Galerkin stencils of the heat operator: in 1-D, R K P on the
+  cell-centred hierarchy is h^-2 (-1/2, 1, -1/2) inside and h^-2 (5/4, -1/2)
+  at a Dirichlet end, and R P is (1/4, 3/2, 1/4); the 2-D stencils are the
+  tensor sums of these;
+* the V-cycle equals a dense-matrix formulation of the same cycle, built from
+  the error-propagation operators of each colour half sweep;
+* with one level the cycle is the exact solve; with exact subsolves the block
+  substitution equals the oracle's exact P^-1;
+* the V-cycle contracts: its convergence factor on the heat blocks stays
+  well below one.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle.amg import (apply_vcycle_preconditioner, colours, hierarchy, prolongation,
+                        restriction, vcycle)
+from oracle.ldu import coefficient_matrix
+from oracle.operators import double_glazing, heat_K, kappa_diffusion_K
+from oracle.precond import apply_inverse
+from oracle.tableau import tableau
+from paper_2010_11377_amd.workloads import gaussian_random_field
+
+
+def _stencil(A, nx, i, j):
+    """3 x 3 stencil of row (i, j) of A, [dy + 1][dx + 1]."""
+    row = A.getrow(j * nx + i).toarray().ravel()
+    st = np.zeros((3, 3))
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            ii, jj = i + dx, j + dy
+            if 0 <= ii < nx and 0 <= jj < A.shape[0] // nx:
+                st[dy + 1, dx + 1] = row[jj * nx + ii]
+    return st
+
+
+def test_transfer_operators():
+    nx, ny = 8, 6
+    P, R = prolongation(nx, ny), restriction(nx, ny)
+    assert P.shape == (48, 12) and R.shape == (12, 48)
+    # R sums 2 x 2 cells
+    assert np.allclose(R @ np.ones(48), 4.0)
+    # P reproduces constants away from the boundary, 3/4 per boundary side
+    p1 = (P @ np.ones(12)).reshape(ny, nx)
+    assert np.allclose(p1[1:-1, 1:-1], 1.0)
+    assert np.isclose(p1[0, 3], 0.75) and np.isclose(p1[0, 0], 0.5625)
+    # weights of fine node (3, 2) (odd column, even row): coarse (1, 1) 9/16,
+    # (2, 1) 3/16, (1, 0) 3/16, (2, 0) 1/16
+    row = P.getrow(2 * nx + 3).toarray().ravel().reshape(ny // 2, nx // 2)
+    assert np.isclose(row[1, 1], 9 / 16) and np.isclose(row[1, 2], 3 / 16)
+    assert np.isclose(row[0, 1], 3 / 16) and np.isclose(row[0, 2], 1 / 16)
+    assert np.isclose(row.sum(), 1.0)
+
+
+def test_galerkin_heat_stencils():
+    n = 16
+    h2 = 1.0 / (1.0 / (n + 1)) ** 2
+    lev = hierarchy(heat_K(n), n, n, coarse_max=1)
+    _, _, S1, K1 = lev[1][:4]
+    nc = n // 2
+    k_in = h2 * np.array([[-0.25, -0.5, -0.25], [-0.5, 3.0, -0.5], [-0.25, -0.5, -0.25]])
+    assert np.allclose(_stencil(K1, nc, 3, 4), k_in, rtol=1e-13, atol=1e-9)
+    m1 = np.array([0.25, 1.5, 0.25])
+    assert np.allclose(_stencil(S1, nc, 3, 4), np.outer(m1, m1), rtol=1e-14)
+    # corner: (5/4)(3/2) + (3/2)(5/4) = 15/4; edge (x = 0, interior y):
+    # (5/4)(3/2) + (3/2)(1) = 27/8
+    assert np.isclose(K1[0, 0], 3.75 * h2, rtol=1e-13)
+    assert np.isclose(K1[4 * nc, 4 * nc], 3.375 * h2, rtol=1e-13)
+    # row sums vanish inside (constants are in the kernel of the Laplacian)
+    assert abs(K1.getrow(4 * nc + 3).sum()) < 1e-9 * h2
+    # levels stop at coarse_max or an odd dimension
+    assert [(l[0], l[1]) for l in hierarchy(heat_K(12), 12, 12, coarse_max=1)] == \
+        [(12, 12), (6, 6), (3, 3)]
+    assert len(hierarchy(heat_K(16), 16, 16, coarse_max=64)) == 2
+
+
+def _dense_cycle(levels, tau, nu, l=0):
+    """Approximate inverse of the V(nu, nu)-cycle on level l as a dense
+    matrix: B = (I - S_post (I - P B_c R D) S_pre) D^-1, with the colour half
+    sweep error propagators G_c = I - Pi_c diag(D)^-1 D."""
+    nx, ny, S, K, P, R = levels[l]
+    D = (S + tau * K).toarray()
+    n = D.shape[0]
+    if P is None:
+        return np.linalg.inv(D)
+    col = colours(nx, ny)
+    G = [np.eye(n) - np.diag((col == c) / np.diag(D)) @ D for c in (0, 1)]
+    pre = np.linalg.matrix_power(G[1] @ G[0], nu)
+    post = np.linalg.matrix_power(G[0] @ G[1], nu)
+    Bc = _dense_cycle(levels, tau, nu, l + 1)
+    E = post @ (np.eye(n) - P.toarray() @ Bc @ R.toarray() @ D) @ pre
+    return (np.eye(n) - E) @ np.linalg.inv(D)
+
+
+@pytest.mark.parametrize("problem", ["heat", "dg", "kappa"])
+@pytest.mark.parametrize("nu", [1, 2])
+def test_vcycle_equals_dense_formulation(problem, nu):
+    n, tau = 16, 3e-4
+    if problem == "heat":
+        K = heat_K(n)
+    elif problem == "dg":
+        K = double_glazing(n, 0.005)[0]
+    else:
+        K = kappa_diffusion_K(np.exp(gaussian_random_field(n + 2, seed=3)))
+    levels = hierarchy(K, n, n, coarse_max=16)
+    assert len(levels) == 3          # 16^2 -> 8^2 -> 4^2
+    b = np.random.default_rng(8).standard_normal(n * n)
+    x = vcycle(levels, tau, b, nu)
+    ref = _dense_cycle(levels, tau, nu) @ b
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_one_level_is_exact_and_rectangular_grids():
+    nx, ny, tau = 12, 10, 1e-3
+    K = heat_K(nx, ny=ny)
+    assert K.shape == (120, 120)
+    b = np.random.default_rng(9).standard_normal(nx * ny)
+    lev = hierarchy(K, nx, ny, coarse_max=1000)
+    assert len(lev) == 1
+    x = vcycle(lev, tau, b)
+    ref = spla.spsolve((sp.identity(nx * ny) + tau * K).tocsc(), b)
+    assert np.linalg.norm(x - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("kind", ["LD", "DU", "GSL", "J"])
+def test_block_substitution_with_exact_subsolves(kind):
+    n, h = 10, 2e-3
+    A, _, _ = tableau("radau_iia", 3)
+    K = double_glazing(n, 0.005)[0]
+    At = coefficient_matrix(A, kind)
+    v = np.random.default_rng(4).standard_normal((3, n * n))
+    z = apply_vcycle_preconditioner(At, K, h, v, n, n, coarse_max=10 ** 6)
+    ref = apply_inverse(At, K, h, v)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_vcycle_convergence_factor():
+    """Stationary iteration x <- x + V(b - D x) in the Poisson limit of the
+    heat blocks (tau h^-2 >> 1): a convergent, contracting cycle on every
+    grid (factor per cycle well below 1)."""
+    tau = 1e3
+    rates = []
+    for n in (32, 64, 128):
+        K = heat_K(n)
+        D = (sp.identity(n * n) + tau * K).tocsr()
+        levels = hierarchy(K, n, n, coarse_max=64)
+        b = np.random.default_rng(n).standard_normal(n * n)
+        x = np.zeros(n * n)
+        res = [np.linalg.norm(b)]
+        for _ in range(6):
+            x = x + vcycle(levels, tau, b - D @ x)
+            res.append(np.linalg.norm(b - D @ x))
+        rates.append((res[-1] / res[2]) ** 0.25)
+    assert max(rates) < 0.3
