@@ -7,9 +7,16 @@ reading taken for the structured finite-difference grids of Sec. 3:
 
 * coarsening: 2 x 2 cells; coarse node (I, J) owns fine columns 2I, 2I+1 and
   rows 2J, 2J+1;
-* prolongation P: cell-centred bilinear interpolation (weights 3/4 and 1/4
-  per direction, 9/16, 3/16, 3/16, 1/16 in 2-D); a coarse neighbour that
-  falls outside the grid contributes nothing;
+* prolongation P: linear interpolation in each direction between the
+  coarse nodes (the centres of the 2 x 2 cells), tensorised in 2-D: fine
+  2I takes 3/4 of coarse I and 1/4 of I-1, fine 2I+1 takes 3/4 of I and 1/4
+  of I+1.  The outermost fine node has no coarse neighbour beyond it; it
+  interpolates between coarse node 0 and the Dirichlet boundary value zero
+  at the boundary's true position.  On the finest grid the boundary lies one
+  spacing h beyond the outermost node, and each coarsening moves the
+  outermost node inwards by half the fine spacing, so on level l the
+  outermost node is (2^l + 1) h / 2 from the boundary and its weight is
+  w_l = (2^l + 1) / (2^(l+1) + 1) (2/3, 3/5, 5/9, ...), not 3/4;
 * restriction R: the sum over each 2 x 2 cell (the transpose of piecewise
   constant interpolation);
 * coarse operators by the Galerkin product: S_{l+1} = R S_l P, K_{l+1} =
@@ -35,22 +42,31 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def _interp_1d(n):
-    """Cell-centred linear interpolation from n // 2 coarse cells to n fine
-    nodes: fine 2I takes 3/4 of I and 1/4 of I-1, fine 2I+1 takes 3/4 of I
-    and 1/4 of I+1 (dropped outside the coarse grid)."""
+def boundary_weight(level):
+    """Weight of the outermost coarse node at the outermost fine node of
+    level ``level``: the ratio of their distances to the boundary."""
+    return (2.0 ** level + 1.0) / (2.0 ** (level + 1) + 1.0)
+
+
+def _interp_1d(n, wb):
+    """Linear interpolation from n // 2 coarse nodes to n fine nodes: fine 2I
+    takes 3/4 of I and 1/4 of I-1, fine 2I+1 takes 3/4 of I and 1/4 of I+1;
+    a fine node whose second coarse node would lie outside the grid takes wb
+    of its own coarse node (the boundary value is zero)."""
     nc = n // 2
     rows, cols, vals = [], [], []
     for i in range(n):
         I = i // 2
+        nb = I - 1 if i % 2 == 0 else I + 1
         rows.append(i)
         cols.append(I)
-        vals.append(0.75)
-        nb = I - 1 if i % 2 == 0 else I + 1
         if 0 <= nb < nc:
+            vals.append(0.75)
             rows.append(i)
             cols.append(nb)
             vals.append(0.25)
+        else:
+            vals.append(wb)
     return sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
 
 
@@ -62,9 +78,10 @@ def _sum_1d(n):
     return sp.csr_matrix((np.ones(2 * nc), (rows, cols)), shape=(nc, n))
 
 
-def prolongation(nx, ny):
-    """P for x-fastest ordering (index = y * nx + x)."""
-    return sp.kron(_interp_1d(ny), _interp_1d(nx), format="csr")
+def prolongation(nx, ny, level=0):
+    """P from level+1 to level, x-fastest ordering (index = y * nx + x)."""
+    wb = boundary_weight(level)
+    return sp.kron(_interp_1d(ny, wb), _interp_1d(nx, wb), format="csr")
 
 
 def restriction(nx, ny):
@@ -79,7 +96,7 @@ def hierarchy(K, nx, ny, coarse_max=64):
     Kl = sp.csr_matrix(K)
     while True:
         if nx * ny > coarse_max and nx % 2 == 0 and ny % 2 == 0 and nx >= 2 and ny >= 2:
-            P, R = prolongation(nx, ny), restriction(nx, ny)
+            P, R = prolongation(nx, ny, len(levels)), restriction(nx, ny)
             levels.append((nx, ny, S, Kl, P, R))
             S = (R @ S @ P).tocsr()
             Kl = (R @ Kl @ P).tocsr()

@@ -128,22 +128,28 @@ Stencil9 identity_stencil(int nx, int ny) {
   return s;
 }
 
-// 1-D cell-centred linear interpolation weights of fine point f onto coarse
-// points: returns the number of parents (1 or 2).
-static int interp1d(int f, int nc, int *J, double *w) {
-  int I = f / 2;
-  int m = 0;
-  J[m] = I;
-  w[m++] = 0.75;
-  int nb = (f % 2 == 0) ? I - 1 : I + 1;
-  if (nb >= 0 && nb < nc) {
-    J[m] = nb;
-    w[m++] = 0.25;
-  }
-  return m;
+double boundary_weight(int level) {
+  const double p = std::ldexp(1.0, level);
+  return (p + 1.0) / (2.0 * p + 1.0);
 }
 
-Stencil9 galerkin(const Stencil9 &A) {
+// 1-D interpolation weights of fine point f onto coarse points: returns the
+// number of parents (1 at the ends of the grid, else 2).
+static int interp1d(int f, int nc, double wb, int *J, double *w) {
+  int I = f / 2;
+  int nb = (f % 2 == 0) ? I - 1 : I + 1;
+  J[0] = I;
+  if (nb >= 0 && nb < nc) {
+    w[0] = 0.75;
+    J[1] = nb;
+    w[1] = 0.25;
+    return 2;
+  }
+  w[0] = wb;
+  return 1;
+}
+
+Stencil9 galerkin(const Stencil9 &A, double wb) {
   const int nx = A.nx, ny = A.ny, ncx = nx / 2, ncy = ny / 2;
   Stencil9 C;
   C.resize(ncx, ncy);
@@ -161,7 +167,7 @@ Stencil9 galerkin(const Stencil9 &A) {
             if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
             int Jx[2], Jy[2];
             double wx[2], wy[2];
-            int mx = interp1d(qx, ncx, Jx, wx), my = interp1d(qy, ncy, Jy, wy);
+            int mx = interp1d(qx, ncx, wb, Jx, wx), my = interp1d(qy, ncy, wb, Jy, wy);
             for (int t = 0; t < my; ++t)
               for (int u = 0; u < mx; ++u) {
                 int ox = Jx[u] - Ix, oy = Jy[t] - Iy;  // in [-1, 1]

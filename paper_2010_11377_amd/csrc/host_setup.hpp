@@ -44,12 +44,21 @@ bool csr_to_stencil(int n, const int *rowptr, const int *colind, const double *v
 // Identity stencil.
 Stencil9 identity_stencil(int nx, int ny);
 
+// Interpolation weight of the outermost coarse node at the outermost fine
+// node of level `level` (0 = finest): the grids are interior nodes of a
+// Dirichlet problem, the boundary one fine spacing beyond the outermost
+// finest node, and each 2 x 2 coarsening moves the outermost node half a
+// spacing inwards, so the weight is the distance ratio
+// (2^l + 1) / (2^(l+1) + 1).
+double boundary_weight(int level);
+
 // Galerkin coarse operator R A P for 2 x 2 coarsening (nx, ny even):
-// P is the tensor product of the 1-D cell-centred linear interpolation
-// (fine 2I gets 3/4 of coarse I and 1/4 of I-1, fine 2I+1 gets 3/4 of I and
-// 1/4 of I+1, missing neighbours dropped) and R = P0^T is the sum over the
-// 2 x 2 aggregate.
-Stencil9 galerkin(const Stencil9 &A);
+// P is the tensor product of the 1-D linear interpolation between cell
+// centres (fine 2I gets 3/4 of coarse I and 1/4 of I-1, fine 2I+1 gets 3/4
+// of I and 1/4 of I+1; the outermost fine node gets wb of its coarse node
+// and nothing from beyond the grid) and R = P0^T is the sum over the 2 x 2
+// aggregate.
+Stencil9 galerkin(const Stencil9 &A, double wb);
 
 // a + t * b, entrywise.
 Stencil9 axpy_stencil(const Stencil9 &a, double t, const Stencil9 &b);

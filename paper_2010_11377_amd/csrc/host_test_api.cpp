@@ -37,10 +37,11 @@ int irkh_csr_to_stencil(int n, const int *rowptr, const int *colind, const doubl
 
 const char *irkh_last_error() { return g_err.c_str(); }
 
-// Galerkin coarse operator of a 9-point stencil (nx, ny even).
-int irkh_galerkin(int nx, int ny, const double *in, double *out) {
-  if (nx % 2 || ny % 2) return -1;
-  Stencil9 C = irk::galerkin(from_flat(nx, ny, in));
+// Galerkin coarse operator of a 9-point stencil (nx, ny even) on hierarchy
+// level `level` (which fixes the boundary interpolation weight).
+int irkh_galerkin(int nx, int ny, int level, const double *in, double *out) {
+  if (nx % 2 || ny % 2 || level < 0) return -1;
+  Stencil9 C = irk::galerkin(from_flat(nx, ny, in), irk::boundary_weight(level));
   to_flat(C, out);
   return 0;
 }

@@ -53,6 +53,40 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
+// Single-workgroup sums of the per-block partials of a reduction (up to
+// tens of thousands of doubles): 1024 threads with eight independent loads in
+// flight each, so the pass is not a chain of dependent memory latencies.  The
+// summation order is fixed for a given n (deterministic).
+constexpr int kRed = 1024;
+
+__device__ __forceinline__ double red_block_sum(double v) {
+  __shared__ double red[kRed / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kRed / 64; ++q) r += red[q];
+  }
+  return r;
+}
+
+__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int n) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = threadIdx.x;
+  for (; b + 7 * kRed < n; b += 8 * kRed) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[b + u * kRed];
+  }
+  for (; b < n; b += kRed) a[0] += p[b];
+  const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  return red_block_sum(t);
+}
+
 // Coefficient k at node p (boundary class q).  A constant-coefficient table
 // has 81 entries and is read through the cache (nearly every lane of a wave
 // reads the same interior entry).
@@ -119,12 +153,10 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kRed)
     k_finalize_norm(const double *__restrict__ partial, int nblk, double *__restrict__ scale,
                     int col, double *__restrict__ norm_out) {
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial[b];
-  const double r = block_sum(acc);
+  const double r = sum_partials(partial, nblk);
   if (threadIdx.x == 0) {
     const double nrm = sqrt(r);
     scale[col] = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
@@ -323,29 +355,24 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kRed)
     k_reduce_cols(const double *__restrict__ partial, int nblk,
                   const KrylovState *__restrict__ ks, int extra, int honor_skip,
                   double *__restrict__ out) {
   const int m = blockIdx.x;
   if (m > ks->j + extra || (honor_skip && ks->skip_reorth)) return;  // uniform per block
-  double acc = 0.0;
-  const double *col = partial + (size_t)m * nblk;
-  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += col[b];
-  const double t = block_sum(acc);
+  const double t = sum_partials(partial + (size_t)m * nblk, nblk);
   if (threadIdx.x == 0) out[m] = t;
 }
 
 // Decide on the second Gram-Schmidt pass (DGKS criterion): mode 0 never,
 // 1 always, 2 when the first pass removed more than half of ||w||^2, i.e.
 // ||v|| < ||w|| / sqrt(2).  Also keeps ||v||^2 of the first pass.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kRed)
     k_reorth_decide(const double *__restrict__ partial_norm, int nblk,
                     const double *__restrict__ h1, KrylovState *__restrict__ ks, int mode,
                     double *__restrict__ norm_sq) {
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial_norm[b];
-  const double nrm2 = block_sum(acc);
+  const double nrm2 = sum_partials(partial_norm, nblk);
   if (threadIdx.x != 0) return;
   const double ww = h1[ks->j + 1];
   const bool skip = (mode == 0) || (mode == 2 && nrm2 > 0.5 * ww);
@@ -356,7 +383,7 @@ __global__ void __launch_bounds__(kBlock)
 // Hessenberg column j: H[:, j] = h1 (+ h2), H[j+1, j] = ||v_{j+1}||, rotate
 // with the stored Givens rotations, form the new one, update g and the
 // residual estimate |g_{j+1}|, set the lazy scale of V_{j+1}, advance j.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kRed)
     k_givens(const double *__restrict__ h1, const double *__restrict__ h2,
              const double *__restrict__ partial_norm, int nblk,
              const double *__restrict__ norm_sq_first, double *__restrict__ H, int ldh,
@@ -364,10 +391,7 @@ __global__ void __launch_bounds__(kBlock)
              double *__restrict__ scale, KrylovState *__restrict__ ks, double beta, double rtol,
              double *__restrict__ host_resid) {
   const bool second = !ks->skip_reorth;
-  double acc = 0.0;
-  if (second)
-    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial_norm[b];
-  const double nrm2s = block_sum(acc);
+  const double nrm2s = second ? sum_partials(partial_norm, nblk) : 0.0;  // uniform branch
   if (threadIdx.x != 0) return;
   const double nrm2 = second ? nrm2s : norm_sq_first[0];
   const int j = ks->j;
@@ -599,7 +623,7 @@ void rhs_copy(const double *rhs, size_t n, double *V0, double *partial, hipStrea
 
 void finalize_norm(const double *partial, int nblk, double *scale, int col, double *norm_out,
                    hipStream_t st) {
-  k_finalize_norm<<<1, kBlock, 0, st>>>(partial, nblk, scale, col, norm_out);
+  k_finalize_norm<<<1, kRed, 0, st>>>(partial, nblk, scale, col, norm_out);
 }
 
 template <typename T>
@@ -662,19 +686,19 @@ void vec_update(double *vin, size_t n, const double *V, const double *scale, con
 
 void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jmax, int extra,
                  int honor_skip, double *out, hipStream_t st) {
-  k_reduce_cols<<<jmax + 1 + extra, kBlock, 0, st>>>(partial, nblk, ks, extra, honor_skip, out);
+  k_reduce_cols<<<jmax + 1 + extra, kRed, 0, st>>>(partial, nblk, ks, extra, honor_skip, out);
 }
 
 void reorth_decide(const double *partial_norm, int nblk, const double *h1, KrylovState *ks,
                    int mode, double *norm_sq, hipStream_t st) {
-  k_reorth_decide<<<1, kBlock, 0, st>>>(partial_norm, nblk, h1, ks, mode, norm_sq);
+  k_reorth_decide<<<1, kRed, 0, st>>>(partial_norm, nblk, h1, ks, mode, norm_sq);
 }
 
 void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
             const double *norm_sq_first, double *H, int ldh, double *cs, double *sn, double *g,
             double *scale, KrylovState *ks, double beta, double rtol, double *host_resid,
             hipStream_t st) {
-  k_givens<<<1, kBlock, 0, st>>>(h1, h2, partial_norm, nblk, norm_sq_first, H, ldh, cs, sn, g,
+  k_givens<<<1, kRed, 0, st>>>(h1, h2, partial_norm, nblk, norm_sq_first, H, ldh, cs, sn, g,
                                  scale, ks, beta, rtol, host_resid);
 }
 

@@ -17,6 +17,9 @@ constexpr int kMaxStages = 8;
 //  npt = 5: only the centre and the four edge neighbours are nonzero.
 //  uniform: constant coefficients whose boundary rows are the interior
 //           stencil without the couplings that leave the grid.
+//  pw:      prolongation weight of the outermost fine node of this level
+//           (linear interpolation towards the zero Dirichlet boundary; the
+//           other fine nodes take 3/4 and 1/4 per direction).
 template <typename T>
 struct OpView {
   int nx, ny;
@@ -24,6 +27,7 @@ struct OpView {
   const T *cls;
   const T *arr;
   int uniform;
+  T pw;
 };
 
 // The coarse end of the hierarchy, solved by one workgroup in LDS: levels
@@ -40,6 +44,7 @@ struct TailDesc {
   size_t off[kTailLevels + 1];  // LDS offset (elements) of level l: b then x; off[nlev] = end
   const T *cls[kTailLevels];
   const T *arr[kTailLevels];
+  T pw[kTailLevels];  // prolongation boundary weight of level l (see OpView)
   const T *CinvT;
 };
 
@@ -113,6 +118,10 @@ void sdown_couple(const OpView<float> &D, const float *interior, const OpView<fl
                   hipStream_t st);
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st);
+// b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K (FP32 z, b).
+void scouple(const OpView<float> &K, const float *k_interior, const double *v,
+             const double *scale_j, const float *z, const double *C, int s, int i, float *b,
+             hipStream_t st);
 // The whole V-cycle below (and including) the first tail level, one workgroup.
 template <typename T>
 size_t vtail_lds_bytes(const TailDesc<T> &td);

@@ -37,7 +37,8 @@ struct DevOp {
   T *arr = nullptr;
   int uniform = 0;
   T interior[9] = {};  // host copy of the interior class (constant coefficients)
-  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform}; }
+  T pw = T(0);         // prolongation boundary weight of this level
+  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform, pw}; }
 };
 
 // A constant-coefficient operator is uniform when every boundary class equals
@@ -237,8 +238,9 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   Kl.push_back(K0);
   while ((long long)Sl.back().nx * Sl.back().ny > S->opt.coarse_max && Sl.back().nx % 2 == 0 &&
          Sl.back().ny % 2 == 0 && Sl.back().nx >= 2 && Sl.back().ny >= 2) {
-    Sl.push_back(irk::galerkin(Sl.back()));
-    Kl.push_back(irk::galerkin(Kl.back()));
+    const double wb = irk::boundary_weight((int)Sl.size() - 1);
+    Sl.push_back(irk::galerkin(Sl.back(), wb));
+    Kl.push_back(irk::galerkin(Kl.back(), wb));
   }
   const int L = (int)Sl.size();
   const long long ncoarse = (long long)Sl.back().nx * Sl.back().ny;
@@ -286,10 +288,13 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
     for (int l = 0; l + 1 < L; ++l) {
       Stencil9 D = irk::axpy_stencil(Sl[l], S->tau[i], Kl[l]);
       const int npt = stencil_npt(D);
-      if (mixed)
+      if (mixed) {
         S->D32[i].push_back(upload_op<float>(S, D, cm, npt));
-      else
+        S->D32[i].back().pw = (float)irk::boundary_weight(l);
+      } else {
         S->D64[i].push_back(upload_op<double>(S, D, cm, npt));
+        S->D64[i].back().pw = irk::boundary_weight(l);
+      }
     }
     Stencil9 Dc = irk::axpy_stencil(Sl[L - 1], S->tau[i], Kl[L - 1]);
     std::vector<double> inv;
@@ -475,6 +480,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
         const DevOp<T> &D = Dops<T>(S)[i][l];
         td.cls[k] = D.cls;
         td.arr[k] = D.arr;
+        td.pw[k] = D.pw;
         if (D.arr) words += 9 * (size_t)D.nx * D.ny;
       }
     }
@@ -496,14 +502,14 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   }
 }
 
-// The coupled finest down pass with two columns per lane (FP32 only).
+// The stage coupling as a streaming pass of its own (FP32 uniform five-point
+// K): b0 = scale_j v_i - K (sum_k C[k] z_k).
 template <typename T>
-void couple_split(irk_solver *S, const DevOp<T> &D, const double *v, const double *scale_j, T *z,
+void couple_split(irk_solver *S, const double *v, const double *scale_j, const T *z,
                   const double *Crow, int i) {
   if constexpr (std::is_same_v<T, float>)
-    irk::kern::sdown_couple(D.view(), D.interior, S->K32.view(), S->K32.interior, S->opt.nu_pre,
-                            v, scale_j, z, Crow, S->s, i, static_cast<float *>(S->b0),
-                            lev_b<float>(S, 1), S->stream);
+    irk::kern::scouple(S->K32.view(), S->K32.interior, v, scale_j, z, Crow, S->s, i,
+                       static_cast<float *>(S->b0), S->stream);
 }
 
 // z = P^-1 v by block substitution (Sec. 4.2).  v = V_j (lazy scale
@@ -520,14 +526,19 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
     // v_i (double), the coupled z_k and the right-hand side b
     const double cbytes = (double)N * (8.0 + es * (ncoup + 1)) +
                           (ncoup ? op_bytes(S, N, S->K64.npt, es) : 0.0);
-    if (S->lt > 0) {
+    const DevOp<T> *D0 = S->lt > 0 ? &Dops<T>(S)[i][0] : nullptr;
+    if (D0 && split_ok<T>(*D0) && split_ok<T>(Kdev<T>(S))) {
+      // streaming coupling pass, then the plain two-columns-per-lane V-cycle
+      ProfTok tk = prof_begin(S, IRK_KC_COUPLE, cbytes);
+      couple_split<T>(S, v, scale_j, z, C + (size_t)i * S->s, i);
+      prof_end(S, tk);
+      vcycle<T>(S, i, b0, z + (size_t)i * N, false);
+    } else if (D0) {
       // coupling fused into the finest-level down pass (+ rc = R(b - D x))
-      const DevOp<T> &D = Dops<T>(S)[i][0];
+      const DevOp<T> &D = *D0;
       ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,
                               cbytes + (double)N * es * 0.25 + op_bytes(S, N, D.npt, es));
-      if (split_ok<T>(D) && split_ok<T>(Kdev<T>(S)))
-        couple_split(S, D, v, scale_j, z, C + (size_t)i * S->s, i);
-      else if (irk::kern::wtile_ok<T>(D.view()) && irk::kern::wtile_ok<T>(Kview<T>(S)))
+      if (irk::kern::wtile_ok<T>(D.view()) && irk::kern::wtile_ok<T>(Kview<T>(S)))
         irk::kern::wdown_couple<T>(D.view(), Kview<T>(S), S->opt.nu_pre, v, scale_j, z,
                                    C + (size_t)i * S->s, S->s, i, b0, lev_b<T>(S, 1), S->stream);
       else

@@ -300,18 +300,20 @@ __global__ void __launch_bounds__(kNT)
 }
 
 // P ec at fine node (fx, fy) from a staged coarse tile with origin (CX0, CY0)
-// and pitch CW.
+// and pitch CW: 3/4 of the own coarse node and 1/4 of the next one in each
+// direction; an outermost fine node (no next coarse node) takes pw of its own.
 template <typename T>
 __device__ __forceinline__ T prolong_value(const T *ec, int CW, int CX0, int CY0, int fx, int fy,
-                                           int ncx, int ncy) {
+                                           int ncx, int ncy, T pw) {
   const int Ix = fx / 2, Iy = fy / 2;
   const int nbx = (fx & 1) ? Ix + 1 : Ix - 1;
   const int nby = (fy & 1) ? Iy + 1 : Iy - 1;
   const bool hx = nbx >= 0 && nbx < ncx, hy = nby >= 0 && nby < ncy;
+  const T wx = hx ? T(0.75) : pw, wy = hy ? T(0.75) : pw;
   const int lx = Ix - CX0, ly = Iy - CY0, nlx = nbx - CX0, nly = nby - CY0;
-  T v = T(0.5625) * ec[ly * CW + lx];
-  if (hx) v += T(0.1875) * ec[ly * CW + nlx];
-  if (hy) v += T(0.1875) * ec[nly * CW + lx];
+  T v = wx * wy * ec[ly * CW + lx];
+  if (hx) v += T(0.25) * wy * ec[ly * CW + nlx];
+  if (hy) v += wx * T(0.25) * ec[nly * CW + lx];
   if (hx && hy) v += T(0.0625) * ec[nly * CW + nlx];
   return v;
 }
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(kNT)
       const int lx = m + q % w, ly = m + q / w;
       const int gx = X0 + lx, gy = Y0 + ly;
       if (gx < 0 || gy < 0 || gx >= D.nx || gy >= D.ny) continue;
-      sx[ly * W + lx] += prolong_value(se, CW, CX0, CY0, gx, gy, ncx, ncy);
+      sx[ly * W + lx] += prolong_value(se, CW, CX0, CY0, gx, gy, ncx, ncy, D.pw);
     }
     __syncthreads();
   }
@@ -482,7 +484,7 @@ __global__ void __launch_bounds__(kTailThreads)
     const int ncx = td.nx[l + 1], ncy = td.ny[l + 1];
     const T *sxc = sm + td.off[l + 1] + (size_t)ncx * ncy;
     for (int p = threadIdx.x; p < n; p += kTailThreads)
-      sx[p] += prolong_value(sxc, ncx, 0, 0, p % nx, p / nx, ncx, ncy);
+      sx[p] += prolong_value(sxc, ncx, 0, 0, p % nx, p / nx, ncx, ncy, td.pw[l]);
     __syncthreads();
     for (int sw = 0; sw < nu; ++sw) {
       tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 1);

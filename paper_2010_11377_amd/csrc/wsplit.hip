@@ -44,6 +44,7 @@ struct Row8s {
 struct SOp {
   int nx, ny;
   float s, w, c, e, n, inv;
+  float pw;  // prolongation weight of the outermost fine node
 };
 
 SOp make_sop(const OpView<float> &D, const float *interior) {
@@ -56,6 +57,7 @@ SOp make_sop(const OpView<float> &D, const float *interior) {
   o.e = interior[5];
   o.n = interior[7];
   o.inv = 1.0f / o.c;
+  o.pw = D.pw;
   return o;
 }
 
@@ -290,18 +292,27 @@ __device__ __forceinline__ void s_up_body(const SOp &o, STile<R> &t, const float
                                           int X0, int Y0) {
   s_pre<BOUND, R, NU>(o, t, X0, Y0);
   // x += P e_c on margin 2 nu - 1: fine column 2I takes 3/4 of coarse column
-  // I and 1/4 of I-1, column 2I+1 3/4 of I and 1/4 of I+1; likewise in y
+  // I and 1/4 of I-1, column 2I+1 3/4 of I and 1/4 of I+1, likewise in y;
+  // the outermost fine column / row takes pw of its coarse node instead (its
+  // second coarse node lies outside the grid, where cr and the neighbour
+  // lanes hold zero)
   constexpr int M = 2 * NU - 1;
   const int gxa = X0 + 2 * s_lane();
   const bool inx = gxa >= 0 && gxa < o.nx;
+  const float wxa = gxa == 0 ? o.pw : 0.75f;
+  const float wxb = gxa + 2 == o.nx ? o.pw : 0.75f;
 #pragma unroll
   for (int r = M; r < R - M; ++r) {
     const int gy = Y0 + r;
     const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
+    const float wy = (gy == 0 || gy == o.ny - 1) ? o.pw : 0.75f;
     const float cj = cr[r / 2 + 1];
     const float cn = cr[(r & 1) ? r / 2 + 2 : r / 2];
-    const float pa = 0.5625f * cj + 0.1875f * s_prev(cj) + 0.1875f * cn + 0.0625f * s_prev(cn);
-    const float pb = 0.5625f * cj + 0.1875f * s_next(cj) + 0.1875f * cn + 0.0625f * s_next(cn);
+    const float ya = wy * cj + 0.25f * cn;                      // own coarse column
+    const float yp = wy * s_prev(cj) + 0.25f * s_prev(cn);      // column I-1
+    const float yn = wy * s_next(cj) + 0.25f * s_next(cn);      // column I+1
+    const float pa = wxa * ya + 0.25f * yp;
+    const float pb = wxb * ya + 0.25f * yn;
     t.xa[r] += in ? pa : 0.0f;
     t.xb[r] += in ? pb : 0.0f;
   }
@@ -345,6 +356,68 @@ __global__ void __launch_bounds__(64 * kSW)
   }
 }
 
+// Block-substitution coupling for stage i (Sec. 4.2) as a streaming pass:
+//   b = scale_j v_i - K c,   c = sum_k C[k] z_k,
+// K uniform five-point.  Each wave covers 124 output columns (two halo
+// columns per side for the east/west couplings of c) and kCRows rows, with
+// c on kCRows + 2 rows in registers.  Every z, v and b element is read or
+// written about once, so the pass runs at streaming bandwidth.
+constexpr int kCRows = 16;
+constexpr int kCTXO = 124;
+
+// The nonzero coupling coefficients of one stage row, compacted on the host:
+// c[m] multiplies z_{k[m]}, m < NK.
+struct CoupleList {
+  float c[kMaxStages];
+  int k[kMaxStages];
+};
+
+template <int NK>
+__global__ void __launch_bounds__(64 * kSW)
+    k_scouple(SOp ko, const double *__restrict__ v, const double *__restrict__ scale_j,
+              const float *__restrict__ z, CoupleList cl, int i, float *__restrict__ b) {
+  const int wave = threadIdx.x >> 6, lane = s_lane();
+  const int OX = blockIdx.x * kCTXO, OY = (blockIdx.y * kSW + wave) * kCRows;
+  if (OY >= ko.ny) return;
+  const int X0 = OX - 2, gxa = X0 + 2 * lane;
+  const size_t N = (size_t)ko.nx * ko.ny;
+  const bool inx = gxa >= 0 && gxa < ko.nx;
+  const bool out = lane >= 1 && lane < 63 && inx;
+  const double sc = *scale_j;
+  float ca[kCRows + 2], cb[kCRows + 2];
+#pragma unroll
+  for (int r = 0; r < kCRows + 2; ++r) {
+    const int gy = OY - 1 + r;
+    float2 acc = make_float2(0.0f, 0.0f);
+    if (inx && gy >= 0 && gy < ko.ny) {
+      const size_t p = (size_t)gy * ko.nx + gxa;
+#pragma unroll
+      for (int m = 0; m < NK; ++m) {
+        const float2 zz = *reinterpret_cast<const float2 *>(z + (size_t)cl.k[m] * N + p);
+        acc.x += cl.c[m] * zz.x;
+        acc.y += cl.c[m] * zz.y;
+      }
+    }
+    ca[r] = acc.x;
+    cb[r] = acc.y;
+  }
+#pragma unroll
+  for (int r = 0; r < kCRows; ++r) {
+    const int gy = OY + r;
+    if (gy >= ko.ny) break;
+    double2 vv = make_double2(0.0, 0.0);
+    if (inx) vv = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * ko.nx + gxa);
+    float va = (float)(sc * vv.x), vb = (float)(sc * vv.y);
+    if (NK > 0) {
+      va -= ko.c * ca[r + 1] + ko.s * ca[r] + ko.n * ca[r + 2] + ko.w * s_prev(cb[r + 1]) +
+            ko.e * cb[r + 1];
+      vb -= ko.c * cb[r + 1] + ko.s * cb[r] + ko.n * cb[r + 2] + ko.w * ca[r + 1] +
+            ko.e * s_next(ca[r + 1]);
+    }
+    if (out) *reinterpret_cast<float2 *>(b + (size_t)gy * ko.nx + gxa) = make_float2(va, vb);
+  }
+}
+
 template <int NU, bool COUPLE>
 dim3 sdown_grid(int nx, int ny) {
   using G = SGeomD<NU, COUPLE>;
@@ -372,6 +445,24 @@ void sdown_couple_nu(const SOp &o, const SOp &ko, const double *v, const double 
 template <int NU>
 void sup_nu(const SOp &o, const float *b, const float *ec, float *x, hipStream_t st) {
   k_sup<NU><<<sup_grid<NU>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+}
+
+void scouple_launch(const SOp &ko, const double *v, const double *scale_j, const float *z,
+                    const CoupleList &cl, int nk, int i, float *b, hipStream_t st) {
+  const dim3 grid((ko.nx + kCTXO - 1) / kCTXO, (ko.ny + kCRows * kSW - 1) / (kCRows * kSW));
+#define L_SCOUPLE(NK_) \
+  k_scouple<NK_><<<grid, 64 * kSW, 0, st>>>(ko, v, scale_j, z, cl, i, b)
+  switch (nk) {
+    case 0: L_SCOUPLE(0); break;
+    case 1: L_SCOUPLE(1); break;
+    case 2: L_SCOUPLE(2); break;
+    case 3: L_SCOUPLE(3); break;
+    case 4: L_SCOUPLE(4); break;
+    case 5: L_SCOUPLE(5); break;
+    case 6: L_SCOUPLE(6); break;
+    default: L_SCOUPLE(7); break;
+  }
+#undef L_SCOUPLE
 }
 
 }  // namespace
@@ -402,6 +493,20 @@ void sdown_couple(const OpView<float> &D, const float *interior, const OpView<fl
   for (int k = 0; k < s; ++k) crow.c[k] = C[k];
   IRK_S_NU(sdown_couple_nu, make_sop(D, interior), make_sop(K, k_interior), v, scale_j, z, crow,
            s, i, b_out, rc, st);
+}
+
+void scouple(const OpView<float> &K, const float *k_interior, const double *v,
+             const double *scale_j, const float *z, const double *C, int s, int i, float *b,
+             hipStream_t st) {
+  CoupleList cl{};
+  int nk = 0;
+  for (int k = 0; k < s; ++k)
+    if (C[k] != 0.0) {
+      cl.c[nk] = (float)C[k];
+      cl.k[nk] = k;
+      ++nk;
+    }
+  scouple_launch(make_sop(K, k_interior), v, scale_j, z, cl, nk, i, b, st);
 }
 
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,

@@ -77,6 +77,7 @@ struct WOp {
   const T *arr;
   T u[9];    // interior class (MODE 0)
   T inv_d;   // 1 / u[4]
+  T pw;      // prolongation weight of the outermost fine node
 };
 
 template <typename T, int NPT, int MODE>
@@ -233,6 +234,7 @@ __device__ __forceinline__ WOp<T> make_wop(const OpView<T> &D) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) o.u[k] = D.cls ? D.cls[36 + k] : T(0);
   o.inv_d = D.cls ? T(1) / o.u[4] : T(0);
+  o.pw = D.pw;
   return o;
 }
 
@@ -342,9 +344,10 @@ __device__ __forceinline__ void wup_body(const WOp<T> &o, T (&x)[R], const T (&b
     if (in_x && gy >= 0 && gy < o.ny) {
       const T *row = se + (Iy - CY0) * CW;
       const T *nrow = se + (nby - CY0) * CW;
-      T pv = T(0.5625) * row[Ix - CX0];
-      if (hx) pv += T(0.1875) * row[nbx - CX0];
-      if (hy) pv += T(0.1875) * nrow[Ix - CX0];
+      const T wx = hx ? T(0.75) : o.pw, wy = hy ? T(0.75) : o.pw;
+      T pv = wx * wy * row[Ix - CX0];
+      if (hx) pv += T(0.25) * wy * row[nbx - CX0];
+      if (hy) pv += wx * T(0.25) * nrow[Ix - CX0];
       if (hx && hy) pv += T(0.0625) * nrow[nbx - CX0];
       x[r] += pv;
     }

@@ -136,7 +136,7 @@ def H():
     pd = ctypes.POINTER(ctypes.c_double)
     pi = ctypes.POINTER(ctypes.c_int)
     L.irkh_csr_to_stencil.argtypes = [ctypes.c_int, pi, pi, pd, ctypes.c_int, ctypes.c_int, pd]
-    L.irkh_galerkin.argtypes = [ctypes.c_int, ctypes.c_int, pd, pd]
+    L.irkh_galerkin.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, pd, pd]
     L.irkh_classify.argtypes = [ctypes.c_int, ctypes.c_int, pd, ctypes.c_double, pd]
     L.irkh_is_symmetric.argtypes = [ctypes.c_int, ctypes.c_int, pd, ctypes.c_double]
     L.irkh_dense_inverse.argtypes = [ctypes.c_int, ctypes.c_int, pd, pd]
@@ -169,20 +169,11 @@ def stencil_to_dense(st, nx, ny):
     return M
 
 
-def prolongation_dense(n):
-    """Cell-centred bilinear interpolation and 2x2 aggregation, as dense
-    matrices built from their definitions."""
-    nc = n // 2
-    P1 = np.zeros((n, nc))
-    R1 = np.zeros((nc, n))
-    for f in range(n):
-        I = f // 2
-        P1[f, I] = 0.75
-        nb = I - 1 if f % 2 == 0 else I + 1
-        if 0 <= nb < nc:
-            P1[f, nb] = 0.25
-        R1[I, f] = 1.0
-    return np.kron(P1, P1), np.kron(R1, R1)
+def transfers_dense(n, level):
+    """The oracle's interpolation and 2x2 aggregation on hierarchy level
+    ``level``, as dense matrices."""
+    from oracle.amg import prolongation, restriction
+    return prolongation(n, n, level).toarray(), restriction(n, n).toarray()
 
 
 def test_stencil_roundtrip(H):
@@ -204,14 +195,14 @@ def test_galerkin_is_dense_triple_product(H, which):
         K = problems.kappa_diffusion(kn)
     st = stencil_of(H, K, n)
     out = np.zeros(9 * (n // 2) ** 2)
-    assert H.irkh_galerkin(n, n, B.dptr(st), B.dptr(out)) == 0
-    P, R = prolongation_dense(n)
+    assert H.irkh_galerkin(n, n, 0, B.dptr(st), B.dptr(out)) == 0
+    P, R = transfers_dense(n, 0)
     ref = R @ problems.to_dense(*K, n * n) @ P
     assert np.allclose(stencil_to_dense(out, n // 2, n // 2), ref, rtol=1e-13, atol=1e-12 * np.abs(ref).max())
-    # two levels down: the product of products
+    # two levels down: the product of products, with the level-1 weights
     out2 = np.zeros(9 * (n // 4) ** 2)
-    assert H.irkh_galerkin(n // 2, n // 2, B.dptr(out), B.dptr(out2)) == 0
-    P2, R2 = prolongation_dense(n // 2)
+    assert H.irkh_galerkin(n // 2, n // 2, 1, B.dptr(out), B.dptr(out2)) == 0
+    P2, R2 = transfers_dense(n // 2, 1)
     assert np.allclose(stencil_to_dense(out2, n // 4, n // 4), R2 @ ref @ P2, atol=1e-12 * np.abs(ref).max())
 
 
@@ -221,11 +212,11 @@ def test_classes(H):
     cls = np.zeros(81)
     assert H.irkh_classify(n, n, B.dptr(st), 1e-12, B.dptr(cls)) == 1
     assert H.irkh_is_symmetric(n, n, B.dptr(st), 1e-13) == 1
-    cur, m = st, n
+    cur, m, lev = st, n, 0
     while m >= 4:
         nxt = np.zeros(9 * (m // 2) ** 2)
-        H.irkh_galerkin(m, m, B.dptr(cur), B.dptr(nxt))
-        cur, m = nxt, m // 2
+        H.irkh_galerkin(m, m, lev, B.dptr(cur), B.dptr(nxt))
+        cur, m, lev = nxt, m // 2, lev + 1
         assert H.irkh_classify(m, m, B.dptr(cur), 1e-12, B.dptr(cls)) == 1
     dg = stencil_of(H, problems.double_glazing(n, 0.005)[:3], n)
     assert H.irkh_classify(n, n, B.dptr(dg), 1e-12, B.dptr(cls)) == 0
