@@ -118,6 +118,16 @@ void sdown_couple(const OpView<float> &D, const float *interior, const OpView<fl
                   hipStream_t st);
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st);
+// FP32 nine-point constant-coefficient levels, two columns per lane
+// (ws9.hip); `classes` is a host copy of the 81 class coefficients.  The down
+// pass stores its pre-smoothed x in xpre (a level-sized buffer), which the up
+// pass starts from.  ws9_ok tells whether the level's grid shape fits the
+// tiling (both passes must run these kernels).
+bool ws9_ok(const OpView<float> &D, int nu);
+void s9down(const OpView<float> &D, const float *classes, int nu, const float *b, float *rc,
+            float *xpre, hipStream_t st);
+void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, const float *ec,
+          const float *xpre, float *x, hipStream_t st);
 // b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K (FP32 z, b).
 void scouple(const OpView<float> &K, const float *k_interior, const double *v,
              const double *scale_j, const float *z, const double *C, int s, int i, float *b,

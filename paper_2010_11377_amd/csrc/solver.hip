@@ -37,6 +37,7 @@ struct DevOp {
   T *arr = nullptr;
   int uniform = 0;
   T interior[9] = {};  // host copy of the interior class (constant coefficients)
+  T classes[81] = {};  // host copy of all nine classes (q * 9 + k)
   T pw = T(0);         // prolongation boundary weight of this level
   OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform, pw}; }
 };
@@ -102,7 +103,7 @@ struct irk_solver {
   double *host_resid = nullptr;  // pinned
   void *Z = nullptr;             // m * sN elements of float or double
   void *b0 = nullptr;            // level-0 right-hand side, N elements
-  void *levb = nullptr, *levx = nullptr;
+  void *levb = nullptr, *levx = nullptr, *levp = nullptr;  // levp: stored pre-smoothed x
   std::vector<size_t> lev_off;
   KrylovState *ks = nullptr;
   size_t partial_len = 0;
@@ -199,6 +200,7 @@ DevOp<T> upload_op(irk_solver *S, const Stencil9 &op, bool use_classes, int npt)
     for (int q = 0; q < 9; ++q)
       for (int k = 0; k < 9; ++k) h[q * 9 + k] = (T)cls[q][k];
     for (int k = 0; k < 9; ++k) d.interior[k] = h[4 * 9 + k];
+    for (int q = 0; q < 81; ++q) d.classes[q] = h[q];
     d.cls = dalloc<T>(S->op_allocs, 81);
     HIP_TRY(hipMemcpy(d.cls, h.data(), 81 * sizeof(T), hipMemcpyHostToDevice));
   } else {
@@ -361,6 +363,7 @@ void alloc_workspace(irk_solver *S) {
   }
   S->levb = dalloc<char>(L, (tot + 1) * es);
   S->levx = dalloc<char>(L, (tot + 1) * es);
+  S->levp = dalloc<char>(L, (tot + 1) * es);
   void *hp = nullptr;
   HIP_TRY(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault));
   S->host_resid = static_cast<double *>(hp);
@@ -416,10 +419,14 @@ template <typename T>
 T *lev_x(irk_solver *S, int l) {
   return static_cast<T *>(S->levx) + S->lev_off[l];
 }
+template <typename T>
+T *lev_p(irk_solver *S, int l) {
+  return static_cast<T *>(S->levp) + S->lev_off[l];
+}
 
 // Fused down / up passes of one level: two columns per lane for FP32 uniform
-// five-point operators, one column per lane for other five-point operators,
-// LDS tiles for nine-point ones.
+// five-point and FP32 constant-coefficient nine-point operators, one column
+// per lane for other five-point operators, LDS tiles for the rest.
 template <typename T>
 bool split_ok(const DevOp<T> &D) {
   if constexpr (std::is_same_v<T, float>)
@@ -429,9 +436,12 @@ bool split_ok(const DevOp<T> &D) {
 }
 
 template <typename T>
-void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, hipStream_t st) {
-  if constexpr (std::is_same_v<T, float>)
+void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
+  if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sdown(D.view(), D.interior, nu, b, rc, st);
+    if (irk::kern::ws9_ok(D.view(), nu))
+      return irk::kern::s9down(D.view(), D.classes, nu, b, rc, xpre, st);
+  }
   if (irk::kern::wtile_ok<T>(D.view()))
     irk::kern::wdown<T>(D.view(), nu, b, rc, st);
   else
@@ -439,9 +449,13 @@ void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, hipStream_t st) {
 }
 
 template <typename T>
-void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, T *x, hipStream_t st) {
-  if constexpr (std::is_same_v<T, float>)
+void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, T *x,
+             hipStream_t st) {
+  if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sup(D.view(), D.interior, nu, b, ec, x, st);
+    if (irk::kern::ws9_ok(D.view(), nu))
+      return irk::kern::s9up(D.view(), D.classes, nu, b, ec, xpre, x, st);
+  }
   if (irk::kern::wtile_ok<T>(D.view()))
     irk::kern::wup<T>(D.view(), nu, b, ec, x, st);
   else
@@ -463,7 +477,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID,
                            (double)n * es * 1.25 + op_bytes(S, n, D.npt, es));
-    down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), st);
+    down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
     prof_end(S, t);
   }
   {
@@ -497,7 +511,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID,
                            (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
-    up_pass<T>(D, nu, bl(l), lev_x<T>(S, l + 1), xl(l), st);
+    up_pass<T>(D, nu, bl(l), lev_x<T>(S, l + 1), lev_p<T>(S, l), xl(l), st);
     prof_end(S, t);
   }
 }

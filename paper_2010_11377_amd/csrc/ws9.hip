@@ -1,0 +1,465 @@
+// Split-column register tiles for FP32 nine-point levels with constant
+// coefficients per boundary class (the Galerkin coarse levels of the heat
+// hierarchy).  Same layout as the five-point split kernels: lane l holds grid
+// columns X0 + 2l (slot a) and X0 + 2l + 1 (slot b) of R rows; slot a of row
+// r has colour r mod 2.
+//
+// Nine-point red-black relaxation is Jacobi within a colour: the diagonal
+// neighbours of a node have its colour, so every update of a half sweep must
+// read old values.  Row r's update reads rows r-1, r, r+1 and only rows r-1
+// and r+1 hold same-colour nodes, so the new value of row r-1 is committed
+// right after row r has been computed: one pending register, no copies.
+//
+// Boundary classes without per-row coefficient sets: the grid height is a
+// multiple of the tile height, and the last tile column is shifted back so
+// that it ends exactly on the grid (it writes only the outputs no other tile
+// writes).  Then the grid's first row can only sit at tile row H, its last
+// row at tile row H + TY - 1, its first column at lane H/2 (slot a) and its
+// last column at lane 63 - H/2 (slot b): compile-time positions.  Other
+// tiles may hold a boundary row or column only at their very edge (distance
+// 0, when TY = H), where the halo has one row of slack; the host refuses
+// grids where a boundary column would fall deeper into a neighbour's halo.
+// Every other row uses the middle-row classes, whose coefficients each lane
+// selects once (first-column, interior or last-column class); only the two
+// boundary rows select their row class at the point of use.  Interior tiles
+// use class 4 from scalar registers.  Nodes outside the grid are held at
+// zero.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace irk {
+namespace {
+
+constexpr int kW9 = 4;  // waves per workgroup, stacked in y
+
+__device__ __forceinline__ int l9() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ float nx9(float v) {  // value of lane + 1 (0 in lane 63)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float pv9(float v) {  // value of lane - 1 (0 in lane 0)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+// Class q = 3 cy + cx (cx, cy: 0 first, 1 inside, 2 last), coefficient
+// k = 3 (dy + 1) + (dx + 1).  Only compile-time indices are used on the
+// device, so the table stays in the kernel-argument segment.
+struct S9Op {
+  int nx, ny;
+  float c[9][9];
+  float inv[9];  // 1 / c[q][4]
+  float pw;      // prolongation weight of the outermost fine node
+};
+
+S9Op make_s9op(const OpView<float> &D, const float *classes) {
+  S9Op o;
+  o.nx = D.nx;
+  o.ny = D.ny;
+  for (int q = 0; q < 9; ++q) {
+    for (int k = 0; k < 9; ++k) o.c[q][k] = classes[q * 9 + k];
+    o.inv[q] = 1.0f / o.c[q][4];
+  }
+  o.pw = D.pw;
+  return o;
+}
+
+template <int R>
+struct T9 {
+  float xa[R], xb[R], ba[R], bb[R];
+};
+
+struct Co {
+  float c[9];
+  float inv;
+  __device__ __forceinline__ float operator[](int k) const { return c[k]; }
+};
+
+// Per-wave tile placement and boundary flags.
+struct Place {
+  int X0, Y0;       // tile origin (halo included)
+  int OXn, OYn;     // first output column / row this wave writes
+  int lo, hi;       // output lanes [lo, hi) (before the shifted-tile cut)
+  bool top, bot;    // grid row 0 at tile row H / row ny-1 at tile row H+TY-1
+  bool fcol, lcol;  // this lane's slot a is column 0 / slot b is column nx-1
+};
+
+// The coefficients of slot a (side 0: first-column class when edge) or slot
+// b (side 2: last-column class when edge) for row class CY.
+template <int CY, int SIDE>
+__device__ __forceinline__ Co side_coefs(const S9Op &o, bool edge) {
+  constexpr int qe = 3 * CY + SIDE, qm = 3 * CY + 1;
+  Co r;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.c[k] = edge ? o.c[qe][k] : o.c[qm][k];
+  r.inv = edge ? o.inv[qe] : o.inv[qm];
+  return r;
+}
+
+// Lane coefficients of the middle rows (selected once per wave).
+struct MidCo {
+  Co a, b;
+};
+
+__device__ __forceinline__ MidCo mid_coefs(const S9Op &o, const Place &p) {
+  MidCo m;
+  m.a = side_coefs<1, 0>(o, p.fcol);
+  m.b = side_coefs<1, 2>(o, p.lcol);
+  return m;
+}
+
+// sum over the eight neighbours of slot a / slot b in row r
+template <int R, typename C>
+__device__ __forceinline__ float offdiag_a(const C &c, const T9<R> &t, int r) {
+  return c[0] * pv9(t.xb[r - 1]) + c[1] * t.xa[r - 1] + c[2] * t.xb[r - 1] +
+         c[3] * pv9(t.xb[r]) + c[5] * t.xb[r] +
+         c[6] * pv9(t.xb[r + 1]) + c[7] * t.xa[r + 1] + c[8] * t.xb[r + 1];
+}
+template <int R, typename C>
+__device__ __forceinline__ float offdiag_b(const C &c, const T9<R> &t, int r) {
+  return c[0] * t.xa[r - 1] + c[1] * t.xb[r - 1] + c[2] * nx9(t.xa[r - 1]) +
+         c[3] * t.xa[r] + c[5] * nx9(t.xa[r]) +
+         c[6] * t.xa[r + 1] + c[7] * t.xb[r + 1] + c[8] * nx9(t.xa[r + 1]);
+}
+
+// Coefficients of slot a / b in tile row r.
+template <bool BOUND, int R, int H, int TY>
+struct Ctx {
+  const S9Op &o;
+  const Place &p;
+  const MidCo &m;
+  __device__ __forceinline__ Co a(int r) const {
+    if (!BOUND) return side_coefs<1, 1>(o, false);
+    if (r == H && p.top) return side_coefs<0, 0>(o, p.fcol);
+    if (r == H + TY - 1 && p.bot) return side_coefs<2, 0>(o, p.fcol);
+    return m.a;
+  }
+  __device__ __forceinline__ Co b(int r) const {
+    if (!BOUND) return side_coefs<1, 1>(o, false);
+    if (r == H && p.top) return side_coefs<0, 2>(o, p.lcol);
+    if (r == H + TY - 1 && p.bot) return side_coefs<2, 2>(o, p.lcol);
+    return m.b;
+  }
+};
+
+// One colour half sweep over rows [M, R-M), Jacobi within the colour.
+template <bool BOUND, int R, int H, int TY, int M>
+__device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t, int color) {
+  const int gxa = cx.p.X0 + 2 * l9();
+  const bool inx = gxa >= 0 && gxa < cx.o.nx;
+  float pend = 0.0f;
+#pragma unroll
+  for (int r = M; r < R - M; ++r) {
+    const int gy = cx.p.Y0 + r;
+    const bool in = !BOUND || (inx && gy >= 0 && gy < cx.o.ny);
+    float v;
+    if ((r & 1) == color) {
+      const Co c = cx.a(r);
+      v = (t.ba[r] - offdiag_a<R>(c, t, r)) * c.inv;
+    } else {
+      const Co c = cx.b(r);
+      v = (t.bb[r] - offdiag_b<R>(c, t, r)) * c.inv;
+    }
+    if (r > M) {  // row r-1 is no longer read by this half sweep
+      if (((r - 1) & 1) == color)
+        t.xa[r - 1] = pend;
+      else
+        t.xb[r - 1] = pend;
+    }
+    pend = in ? v : 0.0f;
+  }
+  constexpr int rl = R - M - 1;
+  if ((rl & 1) == color)
+    t.xa[rl] = pend;
+  else
+    t.xb[rl] = pend;
+}
+
+template <bool BOUND, int R, int H, int TY, int NU>
+__device__ __forceinline__ void s9_pre(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    // from x = 0 the first colour-0 half sweep is x = b / d (b is zero
+    // outside the grid, so this x is too)
+    if ((r & 1) == 0) {
+      t.xa[r] = t.ba[r] * cx.a(r).inv;
+      t.xb[r] = 0.0f;
+    } else {
+      t.xb[r] = t.bb[r] * cx.b(r).inv;
+      t.xa[r] = 0.0f;
+    }
+  }
+  s9_sweep<BOUND, R, H, TY, 1>(cx, t, 1);
+  if (NU >= 2) {
+    s9_sweep<BOUND, R, H, TY, 2>(cx, t, 0);
+    s9_sweep<BOUND, R, H, TY, 3>(cx, t, 1);
+  }
+  if (NU >= 3) {
+    s9_sweep<BOUND, R, H, TY, 4>(cx, t, 0);
+    s9_sweep<BOUND, R, H, TY, 5>(cx, t, 1);
+  }
+}
+
+// Post-smoothing in the reverse colour order (colour 1 first), from x exact
+// on the whole tile (the stored pre-smoothed x plus the coarse correction).
+template <bool BOUND, int R, int H, int TY, int NU>
+__device__ __forceinline__ void s9_post(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t) {
+  s9_sweep<BOUND, R, H, TY, 1>(cx, t, 1);
+  s9_sweep<BOUND, R, H, TY, 2>(cx, t, 0);
+  if (NU >= 2) {
+    s9_sweep<BOUND, R, H, TY, 3>(cx, t, 1);
+    s9_sweep<BOUND, R, H, TY, 4>(cx, t, 0);
+  }
+  if (NU >= 3) {
+    s9_sweep<BOUND, R, H, TY, 5>(cx, t, 1);
+    s9_sweep<BOUND, R, H, TY, 6>(cx, t, 0);
+  }
+}
+
+// rc = R (b - D x), sum over 2 x 2 cells: both slots of one lane, two rows.
+// Writes the coarse nodes of this wave's output rows and lanes.
+template <bool BOUND, int R, int H, int TY>
+__device__ __forceinline__ void s9_restrict(const Ctx<BOUND, R, H, TY> &cx, const T9<R> &t,
+                                            float *__restrict__ rcoarse) {
+  const S9Op &o = cx.o;
+  const Place &p = cx.p;
+  const int lane = l9();
+  const int gxa = p.X0 + 2 * lane;
+  const int ncx = o.nx / 2, ncy = o.ny / 2;
+  const int I = gxa >> 1;
+  const bool inx = gxa >= 0 && gxa < o.nx;
+  const bool lane_out = lane >= p.lo && lane < p.hi && gxa >= p.OXn && I < ncx;
+#pragma unroll
+  for (int r = H; r < R - H; r += 2) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int rr = r + d, gy = p.Y0 + rr;
+      const Co ca = cx.a(rr), cb = cx.b(rr);
+      const float ra = t.ba[rr] - ca.c[4] * t.xa[rr] - offdiag_a<R>(ca, t, rr);
+      const float rb = t.bb[rr] - cb.c[4] * t.xb[rr] - offdiag_b<R>(cb, t, rr);
+      const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
+      sum += in ? ra + rb : 0.0f;
+    }
+    const int gy0 = p.Y0 + r, J = gy0 >> 1;
+    if (lane_out && gy0 >= p.OYn && J < ncy) rcoarse[(size_t)J * ncx + I] = sum;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void s9_load(const float *__restrict__ g, float (&a)[R], float (&b)[R],
+                                        int X0, int Y0, int nx, int ny) {
+  const int gx = X0 + 2 * l9();
+  const bool inx = gx >= 0 && gx < nx;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = Y0 + r;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const float2 *>(g + (size_t)gy * nx + gx);
+    a[r] = v.x;
+    b[r] = v.y;
+  }
+}
+
+__host__ __device__ constexpr int ev9(int h) { return (h + 1) & ~1; }
+
+// Tile geometry: the down pass needs x exact on margin 2 nu for its
+// residual, the up pass (which starts from the stored pre-smoothed x) needs
+// 2 nu post half sweeps: row halo H = 2 nu either way.  In x the up pass
+// needs one more column: the coarse correction of the outermost lanes lacks
+// the coarse column beyond the tile, so its column halo is HX = H + 2.
+// Short tiles (TY rows), so that many waves share a level and each wave's
+// chain of sweeps stays short.
+template <int NU_, int TY_, bool UP_>
+struct G9 {
+  static constexpr int NU = NU_, TY = TY_, H = ev9(2 * NU_);
+  static constexpr int HX = H + (UP_ ? 2 : 0);
+  static constexpr int R = TY + 2 * H;
+  static constexpr int TXO = 128 - 2 * HX;
+};
+constexpr int kTY9 = 8;
+
+// Placement of this wave's tile; false if the wave has no rows.  Needs
+// nx >= TXO and ny a multiple of TY.
+template <typename G>
+__device__ __forceinline__ bool place(const S9Op &o, Place &p) {
+  const int wave = threadIdx.x >> 6;
+  p.OXn = blockIdx.x * G::TXO;
+  p.OYn = (blockIdx.y * kW9 + wave) * G::TY;
+  if (p.OYn >= o.ny) return false;
+  const int OX = min(p.OXn, o.nx - G::TXO), OY = p.OYn;
+  p.X0 = OX - G::HX;
+  p.Y0 = OY - G::H;
+  p.lo = G::HX / 2;
+  p.hi = 64 - G::HX / 2;
+  p.top = OY == 0;
+  p.bot = OY == o.ny - G::TY;
+  const int lane = l9();
+  p.fcol = OX == 0 && lane == G::HX / 2;
+  p.lcol = OX == o.nx - G::TXO && lane == 63 - G::HX / 2;
+  return true;
+}
+
+__device__ __forceinline__ bool boundary_tile(const Place &p, int R, int nx, int ny) {
+  return !(p.X0 >= 1 && p.Y0 >= 1 && p.X0 + 128 <= nx - 1 && p.Y0 + R <= ny - 1);
+}
+
+// Pre-smoothing from zero and rc = R (b - D x); the pre-smoothed x of the
+// output region goes to xpre for the up pass.
+template <int NU, int TY>
+__global__ void __launch_bounds__(64 * kW9)
+    k_s9down(S9Op o, const float *__restrict__ bin, float *__restrict__ rc,
+             float *__restrict__ xpre) {
+  using G = G9<NU, TY, false>;
+  constexpr int H = G::H, R = G::R;
+  Place p;
+  if (!place<G>(o, p)) return;
+  T9<R> t;
+  s9_load<R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
+  if (!boundary_tile(p, R, o.nx, o.ny)) {
+    const MidCo m{};
+    const Ctx<false, R, H, TY> cx{o, p, m};
+    s9_pre<false, R, H, TY, NU>(cx, t);
+    s9_restrict<false, R, H, TY>(cx, t, rc);
+  } else {
+    const MidCo m = mid_coefs(o, p);
+    const Ctx<true, R, H, TY> cx{o, p, m};
+    s9_pre<true, R, H, TY, NU>(cx, t);
+    s9_restrict<true, R, H, TY>(cx, t, rc);
+  }
+  const int lane = l9(), gxa = p.X0 + 2 * lane;
+  if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
+#pragma unroll
+    for (int r = H; r < R - H; ++r) {
+      const int gy = p.Y0 + r;
+      if (gy < o.ny)
+        *reinterpret_cast<float2 *>(xpre + (size_t)gy * o.nx + gxa) = make_float2(t.xa[r], t.xb[r]);
+    }
+  }
+}
+
+// x = xpre + P e_c, then the post-smoothing.
+template <bool BOUND, int R, int H, int TY, int NU>
+__device__ __forceinline__ void s9_up_body(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t,
+                                           const float (&cr)[R / 2 + 3]) {
+  const S9Op &o = cx.o;
+  // fine column 2I takes 3/4 of coarse column I and 1/4 of I-1, column 2I+1
+  // 3/4 of I and 1/4 of I+1, likewise in y; the outermost fine column / row
+  // takes pw of its coarse node (its second coarse node is outside the grid,
+  // where cr and the neighbour lanes hold zero)
+  const int gxa = cx.p.X0 + 2 * l9();
+  const bool inx = gxa >= 0 && gxa < o.nx;
+  const float wxa = gxa == 0 ? o.pw : 0.75f;
+  const float wxb = gxa + 2 == o.nx ? o.pw : 0.75f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = cx.p.Y0 + r;
+    const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
+    const float wy = (gy == 0 || gy == o.ny - 1) ? o.pw : 0.75f;
+    const float cj = cr[r / 2 + 1];
+    const float cn = cr[(r & 1) ? r / 2 + 2 : r / 2];
+    const float ya = wy * cj + 0.25f * cn;
+    const float yp = wy * pv9(cj) + 0.25f * pv9(cn);
+    const float yn = wy * nx9(cj) + 0.25f * nx9(cn);
+    t.xa[r] += in ? wxa * ya + 0.25f * yp : 0.0f;
+    t.xb[r] += in ? wxb * ya + 0.25f * yn : 0.0f;
+  }
+  s9_post<BOUND, R, H, TY, NU>(cx, t);
+}
+
+template <int NU, int TY>
+__global__ void __launch_bounds__(64 * kW9)
+    k_s9up(S9Op o, const float *__restrict__ bin, const float *__restrict__ ec,
+           const float *__restrict__ xpre, float *__restrict__ xout) {
+  using G = G9<NU, TY, true>;
+  constexpr int H = G::H, R = G::R;
+  Place p;
+  if (!place<G>(o, p)) return;
+  const int lane = l9();
+  const int ncx = o.nx / 2, ncy = o.ny / 2;
+  T9<R> t;
+  s9_load<R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
+  s9_load<R>(xpre, t.xa, t.xb, p.X0, p.Y0, o.nx, o.ny);
+  float cr[R / 2 + 3];
+  {
+    const int I = (p.X0 >> 1) + lane;
+#pragma unroll
+    for (int q = 0; q < R / 2 + 3; ++q) {
+      const int J = (p.Y0 >> 1) - 1 + q;
+      cr[q] = (I >= 0 && I < ncx && J >= 0 && J < ncy) ? ec[(size_t)J * ncx + I] : 0.0f;
+    }
+  }
+  if (!boundary_tile(p, R, o.nx, o.ny)) {
+    const MidCo m{};
+    const Ctx<false, R, H, TY> cx{o, p, m};
+    s9_up_body<false, R, H, TY, NU>(cx, t, cr);
+  } else {
+    const MidCo m = mid_coefs(o, p);
+    const Ctx<true, R, H, TY> cx{o, p, m};
+    s9_up_body<true, R, H, TY, NU>(cx, t, cr);
+  }
+  const int gxa = p.X0 + 2 * lane;
+  if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
+#pragma unroll
+    for (int r = H; r < R - H; ++r) {
+      const int gy = p.Y0 + r;
+      if (gy < o.ny)
+        *reinterpret_cast<float2 *>(xout + (size_t)gy * o.nx + gxa) = make_float2(t.xa[r], t.xb[r]);
+    }
+  }
+}
+
+template <typename G>
+dim3 grid9(int nx, int ny) {
+  return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kW9 - 1) / (G::TY * kW9));
+}
+
+// Grid shapes the tiling takes: even dimensions, nx >= 128, ny a multiple of
+// TY, and the grid's last column not inside the halo of the second-to-last
+// tile column (nx mod TXO zero or beyond the halo width H).
+template <typename G>
+bool geometry_ok(int nx, int ny) {
+  const int rx = nx % G::TXO;
+  return nx % 2 == 0 && ny % 2 == 0 && nx >= 128 && ny % G::TY == 0 && (rx == 0 || rx > G::HX);
+}
+
+}  // namespace
+
+namespace kern {
+
+template <int NU>
+bool level_ok(int nx, int ny) {
+  return geometry_ok<G9<NU, kTY9, false>>(nx, ny) && geometry_ok<G9<NU, kTY9, true>>(nx, ny);
+}
+
+bool ws9_ok(const OpView<float> &D, int nu) {
+  if (D.npt != 9 || !D.cls || D.arr) return false;
+  if (nu == 1) return level_ok<1>(D.nx, D.ny);
+  if (nu == 2) return level_ok<2>(D.nx, D.ny);
+  return level_ok<3>(D.nx, D.ny);
+}
+
+#define IRK_S9_NU(KERNEL, UP, ...)                                                           \
+  do {                                                                                       \
+    if (nu == 1)                                                                             \
+      KERNEL<1, kTY9><<<grid9<G9<1, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__);  \
+    else if (nu == 2)                                                                        \
+      KERNEL<2, kTY9><<<grid9<G9<2, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__);  \
+    else                                                                                     \
+      KERNEL<3, kTY9><<<grid9<G9<3, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__);  \
+  } while (0)
+
+void s9down(const OpView<float> &D, const float *classes, int nu, const float *b, float *rc,
+            float *xpre, hipStream_t st) {
+  const S9Op o = make_s9op(D, classes);
+  IRK_S9_NU(k_s9down, false, o, b, rc, xpre);
+}
+
+void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, const float *ec,
+          const float *xpre, float *x, hipStream_t st) {
+  const S9Op o = make_s9op(D, classes);
+  IRK_S9_NU(k_s9up, true, o, b, ec, xpre, x);
+}
+
+}  // namespace kern
+}  // namespace irk

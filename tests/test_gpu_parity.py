@@ -138,7 +138,8 @@ def test_vcycle_preconditioner_contracts(dev, problem):
 
 @pytest.mark.parametrize("problem,nx,ny,precision", [
     ("heat", 200, 136, "mixed"), ("heat", 200, 136, "fp64"), ("heat", 256, 256, "mixed"),
-    ("heat", 512, 512, "mixed"), ("dg", 128, 128, "fp64"), ("dg", 128, 128, "mixed"),
+    ("heat", 512, 512, "mixed"), ("heat", 640, 416, "mixed"), ("heat", 1024, 1024, "mixed"),
+    ("dg", 128, 128, "fp64"), ("dg", 128, 128, "mixed"),
     ("kappa", 128, 128, "fp64")])
 def test_vcycle_preconditioner_matches_oracle(dev, problem, nx, ny, precision):
     """P_LD^-1 v with one V(2,2)-cycle per block against the oracle's plain
