@@ -210,9 +210,10 @@ enum {
   IRK_KC_COUPLE = 4,      /* block-substitution coupling of one stage */
   IRK_KC_VDOWN_L0 = 5,    /* finest level: pre-smoothing + residual + restriction */
   IRK_KC_VUP_L0 = 6,      /* finest level: correction + post-smoothing */
-  IRK_KC_VMID = 7,        /* both passes on the intermediate levels */
+  IRK_KC_VMID_DOWN = 7,   /* intermediate levels: pre-smoothing + residual + restriction */
   IRK_KC_VTAIL = 8,       /* the coarse levels solved in one workgroup */
-  IRK_KC_COUNT = 9
+  IRK_KC_VMID_UP = 9,     /* intermediate levels: correction + post-smoothing */
+  IRK_KC_COUNT = 10
 };
 
 /* Measurement hook: while a class is selected (kc in 0..IRK_KC_COUNT-1),

@@ -18,7 +18,7 @@ IRK_E_HIP = -6
 IRK_E_OOM = -7
 
 KERNEL_CLASSES = ["spmm_dots", "spmm_update", "vec_dots", "vec_update", "couple", "vdown_l0",
-                  "vup_l0", "vmid", "vtail"]
+                  "vup_l0", "vmid_down", "vtail", "vmid_up"]
 
 IRK_FP64 = 0
 IRK_MIXED = 1

@@ -128,10 +128,16 @@ void s9down(const OpView<float> &D, const float *classes, int nu, const float *b
             float *xpre, hipStream_t st);
 void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, const float *ec,
           const float *xpre, float *x, hipStream_t st);
-// b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K (FP32 z, b).
-void scouple(const OpView<float> &K, const float *k_interior, const double *v,
-             const double *scale_j, const float *z, const double *C, int s, int i, float *b,
-             hipStream_t st);
+// b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K on an
+// nx x ny grid with even nx (FP32 z and b, FP64 arithmetic); k_interior is
+// a host copy of K's interior coefficients.
+void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
+             const float *z, const double *C, int s, int i, float *b, hipStream_t st);
+// The FP32 tail with rows in registers (tail2.hip): levels of at most 64 x 64
+// nodes; vtail2_ok tells whether td fits.
+bool vtail2_ok(const TailDesc<float> &td);
+void vtail2(const TailDesc<float> &td, int nu, const float *b, float *x, hipStream_t st);
+size_t vtail2_lds_bytes(const TailDesc<float> &td);
 // The whole V-cycle below (and including) the first tail level, one workgroup.
 template <typename T>
 size_t vtail_lds_bytes(const TailDesc<T> &td);

@@ -475,7 +475,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   for (int l = finest_down_done ? 1 : 0; l < lt; ++l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
-    ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID,
+    ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID_DOWN,
                            (double)n * es * 1.25 + op_bytes(S, n, D.npt, es));
     down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
     prof_end(S, t);
@@ -503,26 +503,33 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t ntop = (size_t)S->lnx[lt] * S->lny[lt];
     words += 2 * ntop + (size_t)S->ncoarse * S->ncoarse;
     ProfTok t = prof_begin(S, IRK_KC_VTAIL, (double)words * es);
-    irk::kern::vtail<T>(td, nu, bl(lt), xl(lt), st);
+    bool done = false;
+    if constexpr (std::is_same_v<T, float>) {
+      if (irk::kern::vtail2_ok(td)) {
+        irk::kern::vtail2(td, nu, bl(lt), xl(lt), st);
+        done = true;
+      }
+    }
+    if (!done) irk::kern::vtail<T>(td, nu, bl(lt), xl(lt), st);
     prof_end(S, t);
   }
   for (int l = lt - 1; l >= 0; --l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
-    ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID,
+    ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID_UP,
                            (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
     up_pass<T>(D, nu, bl(l), lev_x<T>(S, l + 1), lev_p<T>(S, l), xl(l), st);
     prof_end(S, t);
   }
 }
 
-// The stage coupling as a streaming pass of its own (FP32 uniform five-point
-// K): b0 = scale_j v_i - K (sum_k C[k] z_k).
+// The stage coupling as a streaming pass of its own (uniform five-point K,
+// FP32 z, FP64 arithmetic): b0 = scale_j v_i - K (sum_k C[k] z_k).
 template <typename T>
 void couple_split(irk_solver *S, const double *v, const double *scale_j, const T *z,
                   const double *Crow, int i) {
   if constexpr (std::is_same_v<T, float>)
-    irk::kern::scouple(S->K32.view(), S->K32.interior, v, scale_j, z, Crow, S->s, i,
+    irk::kern::scouple(S->nx, S->ny, S->K64.interior, v, scale_j, z, Crow, S->s, i,
                        static_cast<float *>(S->b0), S->stream);
 }
 

@@ -358,23 +358,45 @@ __global__ void __launch_bounds__(64 * kSW)
 
 // Block-substitution coupling for stage i (Sec. 4.2) as a streaming pass:
 //   b = scale_j v_i - K c,   c = sum_k C[k] z_k,
-// K uniform five-point.  Each wave covers 124 output columns (two halo
-// columns per side for the east/west couplings of c) and kCRows rows, with
-// c on kCRows + 2 rows in registers.  Every z, v and b element is read or
-// written about once, so the pass runs at streaming bandwidth.
+// K uniform five-point.  The arithmetic is FP64 (z is read as FP32) and only
+// b is rounded to FP32: for smooth stage vectors K c nearly cancels v_i, and
+// forming the difference in FP32 would leave FP32 noise of the size of v_i in
+// b, which costs the outer FGMRES iterations.  Each wave covers 124 output
+// columns (two halo columns per side for the east/west couplings of c) and
+// kCRows rows, with c on kCRows + 2 rows in registers.  Every z, v and b
+// element is read or written about once: the pass streams.
 constexpr int kCRows = 16;
 constexpr int kCTXO = 124;
+
+// Interior five-point coefficients of K in FP64.
+struct KOpD {
+  int nx, ny;
+  double s, w, c, e, n;
+};
 
 // The nonzero coupling coefficients of one stage row, compacted on the host:
 // c[m] multiplies z_{k[m]}, m < NK.
 struct CoupleList {
-  float c[kMaxStages];
+  double c[kMaxStages];
   int k[kMaxStages];
 };
 
+__device__ __forceinline__ double s_next_d(double v) {  // lane + 1 (0 in lane 63)
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double s_prev_d(double v) {  // lane - 1 (0 in lane 0)
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int NK>
 __global__ void __launch_bounds__(64 * kSW)
-    k_scouple(SOp ko, const double *__restrict__ v, const double *__restrict__ scale_j,
+    k_scouple(KOpD ko, const double *__restrict__ v, const double *__restrict__ scale_j,
               const float *__restrict__ z, CoupleList cl, int i, float *__restrict__ b) {
   const int wave = threadIdx.x >> 6, lane = s_lane();
   const int OX = blockIdx.x * kCTXO, OY = (blockIdx.y * kSW + wave) * kCRows;
@@ -384,22 +406,22 @@ __global__ void __launch_bounds__(64 * kSW)
   const bool inx = gxa >= 0 && gxa < ko.nx;
   const bool out = lane >= 1 && lane < 63 && inx;
   const double sc = *scale_j;
-  float ca[kCRows + 2], cb[kCRows + 2];
+  double ca[kCRows + 2], cb[kCRows + 2];
 #pragma unroll
   for (int r = 0; r < kCRows + 2; ++r) {
     const int gy = OY - 1 + r;
-    float2 acc = make_float2(0.0f, 0.0f);
+    double ax = 0.0, ay = 0.0;
     if (inx && gy >= 0 && gy < ko.ny) {
       const size_t p = (size_t)gy * ko.nx + gxa;
 #pragma unroll
       for (int m = 0; m < NK; ++m) {
         const float2 zz = *reinterpret_cast<const float2 *>(z + (size_t)cl.k[m] * N + p);
-        acc.x += cl.c[m] * zz.x;
-        acc.y += cl.c[m] * zz.y;
+        ax += cl.c[m] * (double)zz.x;
+        ay += cl.c[m] * (double)zz.y;
       }
     }
-    ca[r] = acc.x;
-    cb[r] = acc.y;
+    ca[r] = ax;
+    cb[r] = ay;
   }
 #pragma unroll
   for (int r = 0; r < kCRows; ++r) {
@@ -407,14 +429,15 @@ __global__ void __launch_bounds__(64 * kSW)
     if (gy >= ko.ny) break;
     double2 vv = make_double2(0.0, 0.0);
     if (inx) vv = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * ko.nx + gxa);
-    float va = (float)(sc * vv.x), vb = (float)(sc * vv.y);
+    double va = sc * vv.x, vb = sc * vv.y;
     if (NK > 0) {
-      va -= ko.c * ca[r + 1] + ko.s * ca[r] + ko.n * ca[r + 2] + ko.w * s_prev(cb[r + 1]) +
+      va -= ko.c * ca[r + 1] + ko.s * ca[r] + ko.n * ca[r + 2] + ko.w * s_prev_d(cb[r + 1]) +
             ko.e * cb[r + 1];
       vb -= ko.c * cb[r + 1] + ko.s * cb[r] + ko.n * cb[r + 2] + ko.w * ca[r + 1] +
-            ko.e * s_next(ca[r + 1]);
+            ko.e * s_next_d(ca[r + 1]);
     }
-    if (out) *reinterpret_cast<float2 *>(b + (size_t)gy * ko.nx + gxa) = make_float2(va, vb);
+    if (out) *reinterpret_cast<float2 *>(b + (size_t)gy * ko.nx + gxa) =
+        make_float2((float)va, (float)vb);
   }
 }
 
@@ -447,7 +470,7 @@ void sup_nu(const SOp &o, const float *b, const float *ec, float *x, hipStream_t
   k_sup<NU><<<sup_grid<NU>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
 }
 
-void scouple_launch(const SOp &ko, const double *v, const double *scale_j, const float *z,
+void scouple_launch(const KOpD &ko, const double *v, const double *scale_j, const float *z,
                     const CoupleList &cl, int nk, int i, float *b, hipStream_t st) {
   const dim3 grid((ko.nx + kCTXO - 1) / kCTXO, (ko.ny + kCRows * kSW - 1) / (kCRows * kSW));
 #define L_SCOUPLE(NK_) \
@@ -495,18 +518,18 @@ void sdown_couple(const OpView<float> &D, const float *interior, const OpView<fl
            s, i, b_out, rc, st);
 }
 
-void scouple(const OpView<float> &K, const float *k_interior, const double *v,
-             const double *scale_j, const float *z, const double *C, int s, int i, float *b,
-             hipStream_t st) {
+void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
+             const float *z, const double *C, int s, int i, float *b, hipStream_t st) {
   CoupleList cl{};
   int nk = 0;
   for (int k = 0; k < s; ++k)
     if (C[k] != 0.0) {
-      cl.c[nk] = (float)C[k];
+      cl.c[nk] = C[k];
       cl.k[nk] = k;
       ++nk;
     }
-  scouple_launch(make_sop(K, k_interior), v, scale_j, z, cl, nk, i, b, st);
+  const KOpD ko{nx, ny, k_interior[1], k_interior[3], k_interior[4], k_interior[5], k_interior[7]};
+  scouple_launch(ko, v, scale_j, z, cl, nk, i, b, st);
 }
 
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
