@@ -31,6 +31,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
+# Measured HBM traffic of the SpMM update pass at this workload (rocprofv3
+# FETCH_SIZE / WRITE_SIZE per dispatch, scaled by a 1 GiB copy: FETCH x 2.0,
+# WRITE x 1.0; see profiles/spmm_update_heat2048_gl7_hbm_counters.md), as a
+# function of the Krylov index j.  Valid only for the kernel source it was
+# taken on: reported as null once that file changes.
+SPMM_UPDATE_TRAFFIC = {
+    "source": os.path.join("paper_2010_11377_amd", "csrc", "kernels.hip"),
+    "sha256": "6bd23e4b026226d62e00e727a3c3c849ec4f92125eb08549309152bb05494b61",
+    "fetch_kib": (2.0 * 58548.3, 2.0 * 121240.5),  # a + b (j + 1), scaled
+    "write_kib": 229950.7,
+}
+
+
+def spmm_update_traffic(iters_per_step):
+    """Average measured HBM bytes per spmm_update launch over the timed steps
+    (launch j of a step reads j + 1 basis columns), or None if the kernel
+    source differs from the one measured."""
+    import hashlib
+    rec = SPMM_UPDATE_TRAFFIC
+    try:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+                return None
+    except OSError:
+        return None
+    js = [j for it in iters_per_step for j in range(it)]
+    if not js:
+        return None
+    a, b = rec["fetch_kib"]
+    kib = sum(a + b * (j + 1) + rec["write_kib"] for j in js) / len(js)
+    return kib * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -181,8 +213,10 @@ def main():
     roof = None
     if prof and prof["launches"] > 0 and prof["ms"] > 0:
         achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+        traffic = spmm_update_traffic(head["iters"]) if head["dominant"] == "spmm_update" else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": round(traffic) if traffic else None,
                 "kernel": head["dominant"], "launches": prof["launches"],
                 "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 2),
                 "bytes_per_launch": round(prof["bytes"] / prof["launches"])}
