@@ -103,7 +103,8 @@ struct irk_solver {
   double *host_resid = nullptr;  // pinned
   void *Z = nullptr;             // m * sN elements of float or double
   void *b0 = nullptr;            // level-0 right-hand side, N elements
-  void *levb = nullptr, *levx = nullptr, *levp = nullptr;  // levp: stored pre-smoothed x
+  // levels 1.. of b, x and the stored pre-smoothed x (level 0: b0, z and xp0)
+  void *levb = nullptr, *levx = nullptr, *levp = nullptr, *xp0 = nullptr;
   std::vector<size_t> lev_off;
   KrylovState *ks = nullptr;
   size_t partial_len = 0;
@@ -364,6 +365,7 @@ void alloc_workspace(irk_solver *S) {
   S->levb = dalloc<char>(L, (tot + 1) * es);
   S->levx = dalloc<char>(L, (tot + 1) * es);
   S->levp = dalloc<char>(L, (tot + 1) * es);
+  S->xp0 = dalloc<char>(L, N * es);  // level 0 is not in the level buffers
   void *hp = nullptr;
   HIP_TRY(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault));
   S->host_resid = static_cast<double *>(hp);
@@ -421,7 +423,7 @@ T *lev_x(irk_solver *S, int l) {
 }
 template <typename T>
 T *lev_p(irk_solver *S, int l) {
-  return static_cast<T *>(S->levp) + S->lev_off[l];
+  return l == 0 ? static_cast<T *>(S->xp0) : static_cast<T *>(S->levp) + S->lev_off[l];
 }
 
 // Fused down / up passes of one level: two columns per lane for FP32 uniform

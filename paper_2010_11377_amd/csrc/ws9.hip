@@ -269,7 +269,8 @@ __host__ __device__ constexpr int ev9(int h) { return (h + 1) & ~1; }
 // needs one more column: the coarse correction of the outermost lanes lacks
 // the coarse column beyond the tile, so its column halo is HX = H + 2.
 // Short tiles (TY rows), so that many waves share a level and each wave's
-// chain of sweeps stays short.
+// chain of sweeps stays short; TY must exceed H, or a boundary row would sit
+// inside the second tile's halo with interior coefficients.
 template <int NU_, int TY_, bool UP_>
 struct G9 {
   static constexpr int NU = NU_, TY = TY_, H = ev9(2 * NU_);
@@ -278,6 +279,7 @@ struct G9 {
   static constexpr int TXO = 128 - 2 * HX;
 };
 constexpr int kTY9 = 8;
+static_assert(kTY9 > ev9(2 * 3), "tile height must exceed the row halo for nu <= 3");
 
 // Placement of this wave's tile; false if the wave has no rows.  Needs
 // nx >= TXO and ny a multiple of TY.

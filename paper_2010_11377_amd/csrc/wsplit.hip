@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(64 * kSW)
 // columns (two halo columns per side for the east/west couplings of c) and
 // kCRows rows, with c on kCRows + 2 rows in registers.  Every z, v and b
 // element is read or written about once: the pass streams.
-constexpr int kCRows = 16;
+constexpr int kCRows = 8;
 constexpr int kCTXO = 124;
 
 // Interior five-point coefficients of K in FP64.
