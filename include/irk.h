@@ -83,6 +83,7 @@ typedef struct {
 
 enum { IRK_FP64 = 0, IRK_MIXED = 1 };
 enum { IRK_PREC_LD = 0, IRK_PREC_DU = 1, IRK_PREC_GSL = 2, IRK_PREC_J = 3 };
+enum { IRK_RIGHT = 0, IRK_LEFT = 1 };
 
 typedef struct {
   int precision;   /* IRK_FP64: everything in double.  IRK_MIXED: V-cycles,
@@ -102,7 +103,14 @@ typedef struct {
   int reorth;      /* second classical Gram-Schmidt pass: 0 never, 1 always,
                       2 when the first pass leaves less than 1/sqrt(2) of the
                       vector's norm (DGKS criterion, decided on the GPU) */
-  double rtol;     /* stop when the residual estimate <= rtol * ||rhs|| */
+  double rtol;     /* stop when the residual estimate <= rtol * ||rhs||
+                      (IRK_LEFT: the preconditioned residual, relative to
+                      ||P^-1 rhs||) */
+  int side;        /* IRK_RIGHT: flexible GMRES on A P^-1 (the default).
+                      IRK_LEFT: GMRES on P^-1 A with the preconditioned
+                      residual as stopping test (Sec. 5.1, Tables 7-10);
+                      requires IRK_FP64 and applies to forward steps; adjoint
+                      solves stay right-preconditioned. */
 } irk_options;
 
 typedef struct {
@@ -115,7 +123,7 @@ typedef struct {
 
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
- * true_resid 1, reorth 0, rtol 1e-8. */
+ * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.

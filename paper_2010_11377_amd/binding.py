@@ -22,6 +22,8 @@ KERNEL_CLASSES = ["spmm_dots", "spmm_update", "vec_dots", "vec_update", "couple"
 
 IRK_FP64 = 0
 IRK_MIXED = 1
+IRK_RIGHT = 0
+IRK_LEFT = 1
 PRECOND = {"LD": 0, "DU": 1, "GSL": 2, "J": 3}
 
 
@@ -44,7 +46,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("precond", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("coarse_max", ctypes.c_int), ("vcycles", ctypes.c_int),
-                ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double)]
+                ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("side", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -133,6 +133,8 @@ void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, 
 // a host copy of K's interior coefficients.
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
              const float *z, const double *C, int s, int i, float *b, hipStream_t st);
+// y[j] *= scale[j], j < k (left.hip).
+void scale_by(double *y, const double *scale, int k, hipStream_t st);
 // The FP32 tail with rows in registers (tail2.hip): levels of at most 64 x 64
 // nodes; vtail2_ok tells whether td fits.
 bool vtail2_ok(const TailDesc<float> &td);

@@ -105,6 +105,7 @@ struct irk_solver {
   void *b0 = nullptr;            // level-0 right-hand side, N elements
   // levels 1.. of b, x and the stored pre-smoothed x (level 0: b0, z and xp0)
   void *levb = nullptr, *levx = nullptr, *levp = nullptr, *xp0 = nullptr;
+  double *one = nullptr;  // device constant 1.0
   std::vector<size_t> lev_off;
   KrylovState *ks = nullptr;
   size_t partial_len = 0;
@@ -334,6 +335,11 @@ void alloc_workspace(irk_solver *S) {
   S->f = dalloc<double>(L, N);
   S->g = nullptr;
   S->zero = dalloc<double>(L, sN);
+  {
+    S->one = dalloc<double>(L, 1);
+    const double one = 1.0;
+    HIP_TRY(hipMemcpy(S->one, &one, sizeof one, hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMemset(S->zero, 0, sN * sizeof(double)));
   const size_t nblk_pt = (N + irk::kBlock - 1) / irk::kBlock;
   const size_t nblk_vec = (sN + irk::kBlock * 4 - 1) / (irk::kBlock * 4);
@@ -730,7 +736,141 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
   return status;
 }
 
+// Left-preconditioned GMRES on P^-1 A k = P^-1 rhs (FP64, forward solves):
+// stops when the preconditioned residual estimate |g_{j+1}| <= rtol
+// ||P^-1 rhs|| (the paper's criterion for its left-preconditioned runs,
+// Sec. 5.1, Tables 7-10) and checks the same quantity from the accumulated solution.
+// Each iteration: u = A v_j (into the rhs buffer, unused by forward solves),
+// z = P^-1 u (into Z_j), then two classical Gram-Schmidt passes of z against
+// the basis; the solution is the basis combination V y.
+irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
+  using namespace irk::kern;
+  hipStream_t st = S->stream;
+  const int s = S->s, m = S->opt.restart;
+  const size_t N = S->N, sN = S->sN;
+  const int nblk_pt = (int)((N + irk::kBlock - 1) / irk::kBlock);
+  const int nblk_vec = (int)((sN + irk::kBlock * 4 - 1) / (irk::kBlock * 4));
+  const int nblk_full = (int)((sN + irk::kBlock - 1) / irk::kBlock);
+  const OpView<double> K = S->K64.view();
+  double *Z = static_cast<double *>(S->Z);
+  double *u = S->rhs;
+
+  HIP_TRY(hipMemsetAsync(S->acc, 0, sN * sizeof(double), st));
+  rhs_forward(K, sys.u, S->g, s, S->f, S->V, S->partial, st);
+  // V_0 = P^-1 (1 (x) f), lazily normalised
+  apply_precond<double>(S, S->V, S->one, Z, sys.C, sys.ord);
+  rhs_copy(Z, sN, S->V, S->partial, st);
+  finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
+  HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double beta0 = S->host_resid[0];
+  if (stats) {
+    stats->iters = 0;
+    stats->restarts = 0;
+    stats->rel_resid_est = 0.0;
+    stats->rel_resid_true = -1.0;
+  }
+  if (!std::isfinite(beta0)) {
+    S->err = "non-finite right-hand side";
+    return IRK_E_NONFINITE;
+  }
+  if (beta0 == 0.0) return IRK_OK;
+
+  double beta = beta0, est = 1.0, true_rel = -1.0;
+  int total = 0, restarts = 0;
+  irk_status status = IRK_E_NOT_CONVERGED;
+  while (true) {
+    KrylovState ks0{0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(S->ks, &ks0, sizeof ks0, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(S->gv, &beta, sizeof(double), hipMemcpyHostToDevice, st));
+    int j = 0;
+    bool stop = false;
+    for (; j < m; ++j) {
+      const double *Vj = S->V + (size_t)j * sN;
+      double *Zj = Z + (size_t)j * sN;
+      double *Vn = S->V + (size_t)(j + 1) * sN;
+      kron_apply(K, Vj, sys.hA, s, u, st);
+      apply_precond<double>(S, u, S->scale + j, Zj, sys.C, sys.ord);
+      rhs_copy(Zj, sN, Vn, S->partial, st);
+      // two classical Gram-Schmidt passes (h1, then h2)
+      vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
+      reduce_cols(S->partial, nblk_vec, S->ks, j, 0, 0, S->h1, st);
+      vec_update(nullptr, sN, S->V, S->scale, S->h1, S->ks, S->pnorm, st);
+      reorth_decide(S->pnorm, nblk_vec, S->h1, S->ks, 1, S->norm_dev + 1, st);
+      vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
+      reduce_cols(S->partial, nblk_vec, S->ks, j, 0, 1, S->h2, st);
+      vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm2, st);
+      givens(S->h1, S->h2, S->pnorm2, nblk_vec, S->norm_dev + 1, S->H, m + 1, S->cs, S->sn,
+             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, st);
+      HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      ++total;
+      const double res = S->host_resid[0];
+      const int brk = (int)S->host_resid[1];
+      est = res / beta0;
+      if (brk == 1 || !std::isfinite(res)) {
+        status = IRK_E_BREAKDOWN;
+        S->err = "Krylov breakdown (non-finite or zero Hessenberg entry)";
+        stop = true;
+        ++j;
+        break;
+      }
+      if (res <= S->opt.rtol * beta0 || brk == 2) {
+        status = IRK_OK;
+        stop = true;
+        ++j;
+        break;
+      }
+      if (total >= S->opt.max_iter) {
+        status = IRK_E_NOT_CONVERGED;
+        stop = true;
+        ++j;
+        break;
+      }
+    }
+    if (status == IRK_E_BREAKDOWN) --j;
+    solve_upper(S->H, m + 1, S->gv, j, S->y, st);
+    scale_by(S->y, S->scale, j, st);
+    accumulate_solution<double>(S->V, sN, S->y, j, sN, S->acc, st);
+    if (status == IRK_E_BREAKDOWN || (stop && status == IRK_E_NOT_CONVERGED)) break;
+    if (status == IRK_OK && !S->opt.true_resid) break;
+    // preconditioned residual of the accumulated solution: P^-1 (rhs - A k)
+    residual_full(K, S->acc, sys.hA, s, nullptr, S->f, S->V, S->partial, st);
+    apply_precond<double>(S, S->V, S->one, Z, sys.C, sys.ord);
+    rhs_copy(Z, sN, S->V, S->partial, st);
+    finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
+    HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    beta = S->host_resid[0];
+    true_rel = beta / beta0;
+    if (!std::isfinite(beta)) {
+      status = IRK_E_NONFINITE;
+      S->err = "non-finite residual";
+      break;
+    }
+    if (beta <= S->opt.rtol * beta0) {
+      status = IRK_OK;
+      break;
+    }
+    if (total >= S->opt.max_iter) {
+      status = IRK_E_NOT_CONVERGED;
+      break;
+    }
+    status = IRK_E_NOT_CONVERGED;
+    ++restarts;
+  }
+  if (stats) {
+    stats->iters = total;
+    stats->restarts = restarts;
+    stats->rel_resid_est = est;
+    stats->rel_resid_true = true_rel;
+  }
+  return status;
+}
+
 irk_status run_system(irk_solver *S, const SystemDesc &sys, irk_stats *st) {
+  if (S->opt.side == IRK_LEFT && sys.forward) return gmres_left(S, sys, st);
   if (S->opt.precision == IRK_MIXED) return fgmres<float>(S, sys, st);
   return fgmres<double>(S, sys, st);
 }
@@ -751,6 +891,9 @@ bool valid_options(const irk_options &o, std::string &err) {
   if (o.vcycles != 1) return err = "only one V-cycle per subsolve is implemented", false;
   if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return err = "rtol must be in (0, 1)", false;
   if (o.reorth < 0 || o.reorth > 2) return err = "reorth must be 0, 1 or 2", false;
+  if (o.side != IRK_RIGHT && o.side != IRK_LEFT) return err = "side must be IRK_RIGHT or IRK_LEFT", false;
+  if (o.side == IRK_LEFT && o.precision != IRK_FP64)
+    return err = "left preconditioning needs precision IRK_FP64", false;
   return true;
 }
 
@@ -791,6 +934,7 @@ void irk_default_options(irk_options *o) {
   o->true_resid = 1;
   o->reorth = 0;
   o->rtol = 1e-8;
+  o->side = IRK_RIGHT;
 }
 
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {

@@ -1,16 +1,16 @@
 """GPU tests of the paper's qualitative claims about the preconditioners
-(Sec. 5: Tables 2-9 and the text around them), on finite-difference heat
+(Sec. 5.1: Tables 5-7 and the text around them), on finite-difference heat
 problems.  The paper's iteration counts are FEM + IFISS-AMG specific, so the
 numbers are not targets (their parity is unpinned); the claims checked are:
 
 * ranking: P_LD needs no more outer iterations than P_GSL, and fewer than
-  P_J and P_DU, for s >= 4 stages (Sec. 5.1, Tables 2 and 4; the text's
-  "s = 3 through 7" is read as s >= 4, its own Table 2 having P_GSL ahead at
-  s = 3);
+  P_J and P_DU, for s >= 4 stages (Sec. 5.1.1, Tables 5 and 6: P_LD and
+  P_GSL are close at low stage counts, P_LD's lead grows with s; the
+  condition numbers of Sec. 4.3, Table 2, also put P_GSL ahead at s = 2, 3);
 * the iteration count is roughly independent of the mesh size h_x at a fixed
   number of stages (h_t tied to h_x as in Sec. 5.1: h_t = h_x^((p+1)/q), p = 2,
   q the order of the method);
-* robustness in h_t from 0.05 to 5 at fixed h_x (Sec. 5.3, Tables 6-7).
+* robustness in h_t from 0.05 to 5 at fixed h_x (Sec. 5.1.1, Table 7).
 
 Every count is printed, so a run doubles as the table of iteration counts.
 """

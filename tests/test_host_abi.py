@@ -42,6 +42,7 @@ def test_default_options():
     assert (o.precision, o.precond, o.restart, o.max_iter, o.nu_pre, o.nu_post, o.coarse_max,
             o.vcycles, o.true_resid, o.reorth) == (0, 0, 40, 200, 2, 2, 64, 1, 1, 0)
     assert o.rtol == 1e-8
+    assert o.side == B.IRK_RIGHT
 
 
 def test_status_strings():
@@ -103,6 +104,14 @@ def test_setup_validation_before_any_device_work():
     opt.restart = 0
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
     assert st == B.IRK_E_INVALID and "restart" in msg
+    opt = B.default_options()
+    opt.side = 2
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
+    assert st == B.IRK_E_INVALID and "side" in msg
+    opt = B.default_options()
+    opt.side, opt.precision = B.IRK_LEFT, B.IRK_MIXED
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
+    assert st == B.IRK_E_INVALID and "left" in msg
     # a coupling outside the 3x3 neighbourhood
     ip, ix, d = K
     ix = ix.copy()
