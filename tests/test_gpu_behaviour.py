@@ -10,7 +10,15 @@ numbers are not targets (their parity is unpinned); the claims checked are:
 * the iteration count is roughly independent of the mesh size h_x at a fixed
   number of stages (h_t tied to h_x as in Sec. 5.1: h_t = h_x^((p+1)/q), p = 2,
   q the order of the method);
-* robustness in h_t from 0.05 to 5 at fixed h_x (Sec. 5.1.1, Table 7).
+* robustness in h_t from 0.05 to 5 at fixed h_x (Sec. 5.1.1, Table 7), and
+  at s = 7 P_LD ahead of P_GSL at every h_t, left- and right-preconditioned;
+* double glazing at h_x = 1/128, eps = 0.04, left preconditioning, h_t from
+  0.05 to 5 (Sec. 5.2, Table 13): at s = 7 P_LD needs fewer iterations than
+  P_GSL at every h_t and grows less with h_t; at s = 2 the two stay close and
+  robust.  (With eps = 0.005 and h d_i above about 0.1 the Galerkin coarse
+  operators of the upwind operator under linear interpolation are no longer
+  diagonally dominant and red-black relaxation on them diverges, so that
+  column needs the piecewise-constant interpolation.)
 
 Every count is printed, so a run doubles as the table of iteration counts.
 """
@@ -38,11 +46,11 @@ def dev():
     return torch.device("cuda", 0)
 
 
-def iters(dev, family, s, n, h, precond, precision="fp64", steps=2):
+def iters(dev, family, s, n, h, precond, precision="fp64", steps=2, side="right"):
     from paper_2010_11377_amd.solver import IRKSolver
     A, b, c = tableaux.tableau(family, s)
     S = IRKSolver(A, b, c, problems.heat(n), h, (n, n), precond=precond, precision=precision,
-                  rtol=1e-8, max_iter=400, device=dev)
+                  side=side, rtol=1e-8, max_iter=400, device=dev)
     u = torch.tensor(workloads.fourier_modes(n, seed=0), dtype=torch.float64, device=dev)
     its = []
     for _ in range(steps):
@@ -92,3 +100,54 @@ def test_time_step_robustness(dev, s):
     v = list(counts.values())
     assert max(v) <= 2 * min(v) + 2
     assert max(v) <= 40
+
+
+H_SWEEP = (0.05, 0.1, 0.5, 1.0, 5.0)
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_time_step_ld_vs_gsl(dev, side):
+    n = 128
+    for s in (2, 7):
+        c = {(h, p): iters(dev, "radau_iia", s, n, h, p, side=side)
+             for h in H_SWEEP for p in ("GSL", "LD")}
+        say("case h_t sweep heat 128^2 Radau IIA %d %s: GSL %s LD %s" % (
+            s, side, [c[(h, "GSL")] for h in H_SWEEP], [c[(h, "LD")] for h in H_SWEEP]))
+        for h in H_SWEEP:
+            if s == 7:
+                assert c[(h, "LD")] < c[(h, "GSL")]
+            else:
+                assert abs(c[(h, "LD")] - c[(h, "GSL")]) <= 3
+
+
+def dg_iters(dev, s, n, h, precond, eps, steps=2):
+    from paper_2010_11377_amd.solver import IRKSolver
+    A, b, c = tableaux.tableau("radau_iia", s)
+    ip, ix, d, g = problems.double_glazing(n, eps)
+    S = IRKSolver(A, b, c, (ip, ix, d), h, (n, n), precond=precond, side="left", rtol=1e-8,
+                  max_iter=400, device=dev)
+    S.set_source(g)
+    u = torch.zeros(n * n, dtype=torch.float64, device=dev)
+    its = []
+    for _ in range(steps):
+        u = S.step(u)
+        its.append(S.last_stats.iters)
+    S.close()
+    return max(its)
+
+
+@pytest.mark.parametrize("eps", [0.04])
+def test_double_glazing_time_step(dev, eps):
+    n = 128
+    for s in (2, 7):
+        c = {(h, p): dg_iters(dev, s, n, h, p, eps) for h in H_SWEEP for p in ("GSL", "LD")}
+        gsl = [c[(h, "GSL")] for h in H_SWEEP]
+        ld = [c[(h, "LD")] for h in H_SWEEP]
+        say("case h_t sweep double glazing eps=%g Radau IIA %d (left): GSL %s LD %s" % (
+            eps, s, gsl, ld))
+        if s == 7:
+            assert all(a < b for a, b in zip(ld, gsl))
+            assert gsl[-1] - gsl[0] >= ld[-1] - ld[0]
+        else:
+            assert all(abs(a - b) <= 3 for a, b in zip(ld, gsl))
+            assert max(ld) <= 2 * min(ld) + 2
