@@ -28,7 +28,9 @@ Module map:
   tableau   -- Gauss--Legendre, Radau IIA, Lobatto IIIC tableaux (Sec. 2, Table 1)
   ldu       -- LDU factorisation of A without pivoting and the A~ matrices (Sec. 4.1)
   operators -- finite-difference K and source g for the test problems (Sec. 3)
+  fem       -- linear-element M and K for the heat equation (Sec. 3.1)
   step      -- exact IRK steps (Sec. 2, Sec. 3.1)
   precond   -- exact block preconditioner application (Sec. 4.2)
+  amg       -- the multigrid V-cycle subsolve as read for this path (Sec. 4.2, 5)
   adjoint   -- discrete adjoint step and gradient for kappa-diffusion
 """

@@ -88,11 +88,11 @@ def restriction(nx, ny):
     return sp.kron(_sum_1d(ny), _sum_1d(nx), format="csr")
 
 
-def hierarchy(K, nx, ny, coarse_max=64):
+def hierarchy(K, nx, ny, coarse_max=64, M=None):
     """[(nx_l, ny_l, S_l, K_l, P_l, R_l)] with P_l, R_l the transfers between
-    level l and l+1 (None on the last level)."""
+    level l and l+1 (None on the last level); S_0 = M (the identity if None)."""
     levels = []
-    S = sp.identity(nx * ny, format="csr")
+    S = sp.identity(nx * ny, format="csr") if M is None else sp.csr_matrix(M)
     Kl = sp.csr_matrix(K)
     while True:
         if nx * ny > coarse_max and nx % 2 == 0 and ny % 2 == 0 and nx >= 2 and ny >= 2:
@@ -142,9 +142,10 @@ def vcycle(levels, tau, b, nu=2, level=0):
     return x
 
 
-def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64):
+def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=None):
     """``z ~= P^-1 v`` by block substitution (Sec. 4.2) with one V-cycle per
-    diagonal block ``I + h A~_jj K`` instead of an exact solve (M = I)."""
+    diagonal block ``M + h A~_jj K`` instead of an exact solve (M = I if
+    None)."""
     At = np.asarray(Atilde, dtype=np.float64)
     s = At.shape[0]
     N = K.shape[0]
@@ -152,7 +153,7 @@ def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64):
     upper = np.allclose(At, np.triu(At))
     if not (lower or upper):
         raise ValueError("A~ must be triangular")
-    levels = hierarchy(K, nx, ny, coarse_max)
+    levels = hierarchy(K, nx, ny, coarse_max, M)
     order = range(s) if lower else range(s - 1, -1, -1)
     v = np.asarray(v, dtype=np.float64).reshape(s, N)
     z = np.zeros((s, N))

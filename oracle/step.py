@@ -1,11 +1,11 @@
 """Exact IRK steps: the result the preconditioned Krylov solve converges to.
 
-One step of an s-stage IRK method for ``u' = -K u + g`` (``M = I``) is
-``u_{n+1} = u_n + h sum_i b_i k_i`` (Sec. 2) where the stage vectors solve the
-coupled block system of Sec. 3.1, (3.2), written with Kronecker products in
-Sec. 4:
+One step of an s-stage IRK method for ``M u' = -K u + g`` (``M = I`` for the
+finite-difference operators) is ``u_{n+1} = u_n + h sum_i b_i k_i`` (Sec. 2)
+where the stage vectors solve the coupled block system of Sec. 3.1, (3.2),
+written with Kronecker products in Sec. 4:
 
-    (I_s (x) I + h A (x) K) k = 1_s (x) (g - K u_n).
+    (I_s (x) M + h A (x) K) k = 1_s (x) (g - K u_n).
 
 Three independent routes reach the same ``u_{n+1}``:
 
@@ -15,7 +15,7 @@ Three independent routes reach the same ``u_{n+1}``:
   orthonormal DST-I diagonalises K, so every sine mode obeys its own s x s
   stage system ``(I + h lam A) k^ = 1 (g^ - lam u^)``, solved exactly;
 * ``EigenStepper``   -- ``A = V Lam V^-1`` decouples the stages into s
-  independent systems ``(I + h lam_m K)``, one sparse LU per eigenvalue
+  independent systems ``(M + h lam_m K)``, one sparse LU per eigenvalue
   (conjugate pairs share one), for large variable-coefficient grids.
 
 Test infrastructure only (see the package docstring).
@@ -39,7 +39,7 @@ def stage_matrix(A, K, h, M=None):
 class DirectStepper:
     """Exact step by a sparse LU of the assembled stage matrix (factored once)."""
 
-    def __init__(self, A, b, K, h, g=None):
+    def __init__(self, A, b, K, h, g=None, M=None):
         self.A = np.asarray(A, dtype=np.float64)
         self.b = np.asarray(b, dtype=np.float64)
         self.s = self.A.shape[0]
@@ -47,7 +47,7 @@ class DirectStepper:
         self.N = K.shape[0]
         self.h = float(h)
         self.g = np.zeros(self.N) if g is None else np.asarray(g, dtype=np.float64)
-        self.lu = spla.splu(stage_matrix(self.A, self.K, self.h))
+        self.lu = spla.splu(stage_matrix(self.A, self.K, self.h, None if M is None else M.tocsr()))
 
     def stages(self, u):
         """Stage vectors k, shape (s, N), for the step from u."""
@@ -101,11 +101,11 @@ class EigenStepper:
     """Exact step through the eigen-decomposition ``A = V diag(lam) V^-1``.
 
     With ``k~ = (V^-1 (x) I) k`` the stage system splits into
-    ``(I + h lam_m K) k~_m = (V^-1 1)_m f`` with ``f = g - K u_n``, and
+    ``(M + h lam_m K) k~_m = (V^-1 1)_m f`` with ``f = g - K u_n``, and
     ``u_{n+1} = u_n + h sum_m (b^T V)_m k~_m``.  Conjugate eigenvalues give
     conjugate terms, so one complex LU per pair is enough."""
 
-    def __init__(self, A, b, K, h, g=None):
+    def __init__(self, A, b, K, h, g=None, M=None):
         A = np.asarray(A, dtype=np.float64)
         b = np.asarray(b, dtype=np.float64)
         self.K = K.tocsr()
@@ -116,7 +116,7 @@ class EigenStepper:
         w_in = np.linalg.solve(V, np.ones(A.shape[0]))     # V^-1 1
         w_out = b @ V                                       # b^T V
         self.terms = []
-        I = sp.identity(self.N, format="csc")
+        Mm = sp.identity(self.N, format="csc") if M is None else sp.csc_matrix(M)
         used = np.zeros(lam.size, dtype=bool)
         for m in range(lam.size):
             if used[m]:
@@ -128,9 +128,9 @@ class EigenStepper:
                 partner = np.argmin(np.abs(lam - np.conj(lam[m])) + used * 1e300)
                 used[partner] = True
                 mult = 2.0
-                lu = spla.splu((I + self.h * lam[m] * self.K.astype(np.complex128)).tocsc())
+                lu = spla.splu((Mm + self.h * lam[m] * self.K.astype(np.complex128)).tocsc())
             else:
-                lu = spla.splu((I + self.h * lam[m].real * self.K).tocsc())
+                lu = spla.splu((Mm + self.h * lam[m].real * self.K).tocsc())
             self.terms.append((lu, w_in[m] * w_out[m], mult))
 
     def step(self, u):
