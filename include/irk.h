@@ -18,9 +18,11 @@
  *       substitution over the stage blocks, one AMG V-cycle on each
  *       diagonal block  M + h A~_ii K.
  *
- * The paper's stiffness matrix F is called K here.  Only M = I is supported
- * (finite differences); K must be a 5-point stencil on a structured nx x ny
- * grid (x fastest) given as CSR.
+ * The paper's stiffness matrix F is called K here.  K and the mass matrix M
+ * (NULL: M = I, the finite-difference case) are CSR matrices on a structured
+ * nx x ny grid (x fastest) whose couplings stay within the 3 x 3 neighbourhood
+ * of a node (five-point finite differences, seven-point P1 elements on right
+ * triangles, nine-point stencils).
  *
  * Conventions for every call:
  *  - "host" pointers are read during the call and copied; the caller keeps
@@ -133,11 +135,13 @@ void irk_default_options(irk_options *opt);
  * |d_k| <= 64 * eps * max|a_ij|, IRK_E_INVALID for s outside 1..8. */
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U);
 
-/* Build a solver for the stage system of Sec. 3.1 / Sec. 4 with M = I
- * (M must be NULL), stiffness K (host CSR, copied), timestep h_t > 0 and the
- * structured grid (required).  Factors A (Sec. 4.1), builds the AMG
- * hierarchy of every diagonal block I + h_t A~_ii K, uploads it and
- * allocates the Krylov workspace on the current HIP device.  hip_stream is a
+/* Build a solver for the stage system of Sec. 3.1 / Sec. 4 with mass matrix
+ * M (host CSR, copied; NULL for M = I; positive diagonal required), stiffness
+ * K (host CSR, copied), timestep h_t > 0 and the structured grid (required).
+ * Factors A (Sec. 4.1), builds the AMG hierarchy of every diagonal block
+ * M + h_t A~_ii K, uploads it and allocates the Krylov workspace on the
+ * current HIP device.  IRK_E_INVALID when M and K differ in size or M has a
+ * coupling outside the 3 x 3 neighbourhood or a non-positive diagonal.  hip_stream is a
  * hipStream_t (NULL for the default stream).  opt may be NULL (defaults).
  * On success *out owns all device memory until irk_destroy. */
 irk_status irk_setup(irk_solver **out, const irk_butcher *tab, const irk_csr *M,
@@ -169,7 +173,8 @@ irk_status irk_step_stages(irk_solver *S, const double *u_n_dev, double *u_np1_d
  * transposed preconditioner P^T (block back substitution for P_LD), and
  * writes lam_n = lam_np1 - K^T sum_i psi_i.  Optionally writes psi and the
  * stage values U_i = u_n + h sum_j a_ij k_j (device, s*N doubles each; NULL
- * skips).  Requires a symmetric K.  lam_n_dev may alias lam_np1_dev. */
+ * skips).  Requires a symmetric K and M = I (IRK_E_INVALID otherwise).
+ * lam_n_dev may alias lam_np1_dev. */
 irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *lam_np1_dev,
                             double *lam_n_dev, double *psi_dev, double *U_dev, irk_stats *st);
 
@@ -183,7 +188,7 @@ irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *
 irk_status irk_grad_diffusion_nodes(irk_solver *S, const double *psi_dev, const double *U_dev,
                                     double h_x, double *gnode_dev);
 
-/* The Kronecker SpMM alone: y = (I_s (x) I + h A (x) K) x (Sec. 4), x and y
+/* The Kronecker SpMM alone: y = (I_s (x) M + h A (x) K) x (Sec. 4), x and y
  * device arrays of s*N doubles (stage-major), no aliasing. */
 irk_status irk_apply_operator(irk_solver *S, const double *x_dev, double *y_dev);
 

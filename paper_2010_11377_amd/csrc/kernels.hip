@@ -205,39 +205,49 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 // Kronecker SpMM with fused Gram-Schmidt
 
-// w_i(p) = z_i(p) + sum_k hA[i][k] (K z_k)(p) for all s stages at node p.
-template <typename TZ, int S>
-__device__ __forceinline__ void kron_apply(const OpView<double> &K, 
+// w_i(p) = (M z_i)(p) + sum_k hA[i][k] (K z_k)(p) for all s stages at node p
+// (Sec. 4: the stage matrix I_s (x) M + h A (x) K); M = I unless MASS.
+template <typename TZ, int S, bool MASS>
+__device__ __forceinline__ void kron_apply(const OpView<double> &K, const OpView<double> &M,
                                            const TZ *__restrict__ z, const Mat8 &hA, size_t p,
                                            size_t N, double *w) {
   const int i = (int)(p % K.nx), j = (int)(p / K.nx);
   const int q = node_class_d(i, j, K.nx, K.ny);
-  double kz[S];
+  double kz[S], mz[S];
 #pragma unroll
-  for (int st = 0; st < S; ++st) kz[st] = 0.0;
+  for (int st = 0; st < S; ++st) kz[st] = mz[st] = 0.0;
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    if (K.npt == 5 && (t == 0 || t == 2 || t == 6 || t == 8)) continue;
+    const bool corner = t == 0 || t == 2 || t == 6 || t == 8;
+    const bool kt = !(K.npt == 5 && corner);
+    const bool mt = MASS && !(M.npt == 5 && corner);
+    if (!kt && !mt) continue;
     const int dx = t % 3 - 1, dy = t / 3 - 1;
     const int xi = i + dx, yj = j + dy;
     if (xi < 0 || xi >= K.nx || yj < 0 || yj >= K.ny) continue;
     const size_t pn = (size_t)yj * K.nx + xi;
-    const double a = coef(K, q, t, p, N);
+    const double a = kt ? coef(K, q, t, p, N) : 0.0;
+    const double m = mt ? coef(M, q, t, p, N) : 0.0;
 #pragma unroll
-    for (int st = 0; st < S; ++st) kz[st] += a * double(z[(size_t)st * N + pn]);
+    for (int st = 0; st < S; ++st) {
+      const double zv = double(z[(size_t)st * N + pn]);
+      kz[st] += a * zv;
+      if (MASS) mz[st] += m * zv;
+    }
   }
 #pragma unroll
   for (int r = 0; r < S; ++r) {
-    double acc = double(z[(size_t)r * N + p]);
+    double acc = MASS ? mz[r] : double(z[(size_t)r * N + p]);
 #pragma unroll
     for (int st = 0; st < S; ++st) acc += hA.a[r * 8 + st] * kz[st];
     w[r] = acc;
   }
 }
 
-template <typename TZ, int S>
+template <typename TZ, int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
-    k_spmm_dots(OpView<double> K, const TZ *__restrict__ z, Mat8 hA, const double *__restrict__ V,
+    k_spmm_dots(OpView<double> K, OpView<double> M, const TZ *__restrict__ z, Mat8 hA,
+                const double *__restrict__ V,
                 const double *__restrict__ scale, const KrylovState *__restrict__ ks,
                 double *__restrict__ partial) {
   const size_t N = (size_t)K.nx * K.ny;
@@ -247,7 +257,7 @@ __global__ void __launch_bounds__(kBlock)
   const int jj = ks->j;
   double w[S];
   const bool live = p < N;
-  if (live) kron_apply<TZ, S>(K, z + (size_t)jj * sN, hA, p, N, w);
+  if (live) kron_apply<TZ, S, MASS>(K, M, z + (size_t)jj * sN, hA, p, N, w);
   for (int m = 0; m <= jj; ++m) {
     double acc = 0.0;
     if (live) {
@@ -269,9 +279,9 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) partial[(size_t)(jj + 1) * nblk + blockIdx.x] = t;
 }
 
-template <typename TZ, int S>
+template <typename TZ, int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
-    k_spmm_update(OpView<double> K, const TZ *__restrict__ z, Mat8 hA,
+    k_spmm_update(OpView<double> K, OpView<double> M, const TZ *__restrict__ z, Mat8 hA,
                   const double *__restrict__ V, const double *__restrict__ scale,
                   const double *__restrict__ hcol, const KrylovState *__restrict__ ks,
                   double *__restrict__ Vall, double *__restrict__ partial) {
@@ -282,7 +292,7 @@ __global__ void __launch_bounds__(kBlock)
   double val = 0.0;
   if (p < N) {
     double w[S];
-    kron_apply<TZ, S>(K, z + (size_t)jj * sN, hA, p, N, w);
+    kron_apply<TZ, S, MASS>(K, M, z + (size_t)jj * sN, hA, p, N, w);
     for (int m = 0; m <= jj; ++m) {
       const double c = hcol[m] * scale[m];
       const double *Vm = V + (size_t)m * sN;
@@ -460,9 +470,9 @@ __global__ void __launch_bounds__(kBlock)
   u_out[p] = a;
 }
 
-template <int S>
+template <int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
-    k_residual_full(OpView<double> K, const double *__restrict__ x, Mat8 hA,
+    k_residual_full(OpView<double> K, OpView<double> M, const double *__restrict__ x, Mat8 hA,
                     const double *__restrict__ rhs, const double *__restrict__ f,
                     double *__restrict__ V0, double *__restrict__ partial) {
   const size_t N = (size_t)K.nx * K.ny;
@@ -470,7 +480,7 @@ __global__ void __launch_bounds__(kBlock)
   double val = 0.0;
   if (p < N) {
     double w[S];
-    kron_apply<double, S>(K, x, hA, p, N, w);
+    kron_apply<double, S, MASS>(K, M, x, hA, p, N, w);
 #pragma unroll
     for (int r = 0; r < S; ++r) {
       const double b = rhs ? rhs[(size_t)r * N + p] : f[p];
@@ -483,14 +493,15 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-template <int S>
+template <int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
-    k_kron_out(OpView<double> K, const double *__restrict__ x, Mat8 hA, double *__restrict__ y) {
+    k_kron_out(OpView<double> K, OpView<double> M, const double *__restrict__ x, Mat8 hA,
+               double *__restrict__ y) {
   const size_t N = (size_t)K.nx * K.ny;
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= N) return;
   double w[S];
-  kron_apply<double, S>(K, x, hA, p, N, w);
+  kron_apply<double, S, MASS>(K, M, x, hA, p, N, w);
 #pragma unroll
   for (int r = 0; r < S; ++r) y[(size_t)r * N + p] = w[r];
 }
@@ -645,28 +656,41 @@ void couple(const OpView<T> &K, const double *v, const double *scale_j, const T 
     default: KERNEL(8, __VA_ARGS__); break;                \
   }
 
+// M == nullptr: the identity mass matrix.
 template <typename TZ>
-void spmm_dots(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
-               const double *scale, const KrylovState *ks, int jmax, double *partial,
-               hipStream_t st) {
+void spmm_dots(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
+               int s, const double *V, const double *scale, const KrylovState *ks, int jmax,
+               double *partial, hipStream_t st) {
   (void)jmax;
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
-#define L_SPMM_DOTS(S_, dummy) \
-  k_spmm_dots<TZ, S_><<<nblocks(N), kBlock, 0, st>>>(K, z, m, V, scale, ks, partial)
-  IRK_DISPATCH_S(s, L_SPMM_DOTS, 0)
+  const OpView<double> Mv = M ? *M : K;
+#define L_SPMM_DOTS(S_, MS_)                                                          \
+  k_spmm_dots<TZ, S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, z, m, V, scale, ks, \
+                                                          partial)
+  if (M) {
+    IRK_DISPATCH_S(s, L_SPMM_DOTS, true)
+  } else {
+    IRK_DISPATCH_S(s, L_SPMM_DOTS, false)
+  }
 #undef L_SPMM_DOTS
 }
 
 template <typename TZ>
-void spmm_update(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
-                 const double *scale, const double *hcol, const KrylovState *ks, double *vout,
-                 double *partial, hipStream_t st) {
+void spmm_update(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
+                 int s, const double *V, const double *scale, const double *hcol,
+                 const KrylovState *ks, double *vout, double *partial, hipStream_t st) {
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
-#define L_SPMM_UPD(S_, dummy) \
-  k_spmm_update<TZ, S_><<<nblocks(N), kBlock, 0, st>>>(K, z, m, V, scale, hcol, ks, vout, partial)
-  IRK_DISPATCH_S(s, L_SPMM_UPD, 0)
+  const OpView<double> Mv = M ? *M : K;
+#define L_SPMM_UPD(S_, MS_)                                                              \
+  k_spmm_update<TZ, S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, z, m, V, scale, hcol, ks, \
+                                                            vout, partial)
+  if (M) {
+    IRK_DISPATCH_S(s, L_SPMM_UPD, true)
+  } else {
+    IRK_DISPATCH_S(s, L_SPMM_UPD, false)
+  }
 #undef L_SPMM_UPD
 }
 
@@ -717,23 +741,33 @@ void combine_stages(const double *u_in, const double *x, const double *wts, int 
   k_combine<<<nblocks(N), kBlock, 0, st>>>(u_in, x, pack_row(wts, s), s, N, u_out);
 }
 
-void residual_full(const OpView<double> &K, const double *x, const double *hA, int s,
-                   const double *rhs, const double *f, double *V0, double *partial,
-                   hipStream_t st) {
+void residual_full(const OpView<double> &K, const OpView<double> *M, const double *x,
+                   const double *hA, int s, const double *rhs, const double *f, double *V0,
+                   double *partial, hipStream_t st) {
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
-#define L_RES(S_, dummy) \
-  k_residual_full<S_><<<nblocks(N), kBlock, 0, st>>>(K, x, m, rhs, f, V0, partial)
-  IRK_DISPATCH_S(s, L_RES, 0)
+  const OpView<double> Mv = M ? *M : K;
+#define L_RES(S_, MS_) \
+  k_residual_full<S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, x, m, rhs, f, V0, partial)
+  if (M) {
+    IRK_DISPATCH_S(s, L_RES, true)
+  } else {
+    IRK_DISPATCH_S(s, L_RES, false)
+  }
 #undef L_RES
 }
 
-void kron_apply(const OpView<double> &K, const double *x, const double *hA, int s, double *y,
-                hipStream_t st) {
+void kron_apply(const OpView<double> &K, const OpView<double> *M, const double *x,
+                const double *hA, int s, double *y, hipStream_t st) {
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
-#define L_KRON(S_, dummy) k_kron_out<S_><<<nblocks(N), kBlock, 0, st>>>(K, x, m, y)
-  IRK_DISPATCH_S(s, L_KRON, 0)
+  const OpView<double> Mv = M ? *M : K;
+#define L_KRON(S_, MS_) k_kron_out<S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, x, m, y)
+  if (M) {
+    IRK_DISPATCH_S(s, L_KRON, true)
+  } else {
+    IRK_DISPATCH_S(s, L_KRON, false)
+  }
 #undef L_KRON
 }
 
@@ -768,18 +802,20 @@ template void couple<float>(const OpView<float> &, const double *, const double 
                             const double *, int, int, float *, hipStream_t);
 template void couple<double>(const OpView<double> &, const double *, const double *,
                              const double *, const double *, int, int, double *, hipStream_t);
-template void spmm_dots<float>(const OpView<double> &, const float *, const double *, int,
-                               const double *, const double *, const KrylovState *, int, double *,
-                               hipStream_t);
-template void spmm_dots<double>(const OpView<double> &, const double *, const double *, int,
-                                const double *, const double *, const KrylovState *, int,
-                                double *, hipStream_t);
-template void spmm_update<float>(const OpView<double> &, const float *, const double *, int,
-                                 const double *, const double *, const double *,
-                                 const KrylovState *, double *, double *, hipStream_t);
-template void spmm_update<double>(const OpView<double> &, const double *, const double *, int,
-                                  const double *, const double *, const double *,
-                                  const KrylovState *, double *, double *, hipStream_t);
+template void spmm_dots<float>(const OpView<double> &, const OpView<double> *, const float *,
+                               const double *, int, const double *, const double *,
+                               const KrylovState *, int, double *, hipStream_t);
+template void spmm_dots<double>(const OpView<double> &, const OpView<double> *, const double *,
+                                const double *, int, const double *, const double *,
+                                const KrylovState *, int, double *, hipStream_t);
+template void spmm_update<float>(const OpView<double> &, const OpView<double> *, const float *,
+                                 const double *, int, const double *, const double *,
+                                 const double *, const KrylovState *, double *, double *,
+                                 hipStream_t);
+template void spmm_update<double>(const OpView<double> &, const OpView<double> *, const double *,
+                                  const double *, int, const double *, const double *,
+                                  const double *, const KrylovState *, double *, double *,
+                                  hipStream_t);
 template void accumulate_solution<float>(const float *, size_t, const double *, int, size_t,
                                          double *, hipStream_t);
 template void accumulate_solution<double>(const double *, size_t, const double *, int, size_t,

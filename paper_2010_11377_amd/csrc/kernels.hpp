@@ -147,19 +147,19 @@ template <typename T>
 void vtail(const TailDesc<T> &td, int nu, const T *b, T *x, hipStream_t st);
 
 // Kronecker SpMM with fused classical Gram-Schmidt dots:
-//   w = z + (hA (x) K) z  (M = I), z = Z_j (TZ, stage-major)
+//   w = (I (x) M) z + (hA (x) K) z, z = Z_j (TZ, stage-major); M == nullptr: M = I
 //   partial[m * nblk + blk] = block sum of <V_m, w> * scale_m, m = 0..j
 template <typename TZ>
-void spmm_dots(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
-               const double *scale, const KrylovState *ks, int jmax, double *partial,
-               hipStream_t st);
+void spmm_dots(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
+               int s, const double *V, const double *scale, const KrylovState *ks, int jmax,
+               double *partial, hipStream_t st);
 
-// w = z + (hA (x) K) z recomputed; vout = w - sum_{m<=j} hcol[m] scale_m V_m;
+// w = (I (x) M) z + (hA (x) K) z recomputed; vout = w - sum_{m<=j} hcol[m] scale_m V_m;
 // partial[blk] = block sum of vout^2.
 template <typename TZ>
-void spmm_update(const OpView<double> &K, const TZ *z, const double *hA, int s, const double *V,
-                 const double *scale, const double *hcol, const KrylovState *ks, double *vout,
-                 double *partial, hipStream_t st);
+void spmm_update(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
+                 int s, const double *V, const double *scale, const double *hcol,
+                 const KrylovState *ks, double *vout, double *partial, hipStream_t st);
 
 // Second Gram-Schmidt pass: partial dots of vin with V_0..V_j.
 void vec_dots(const double *vin, size_t n, const double *V, const double *scale,
@@ -196,15 +196,16 @@ void accumulate_solution(const TZ *Z, size_t zs, const double *y, int k, size_t 
 void combine_stages(const double *u_in, const double *x, const double *wts, int s, size_t N,
                     double *u_out, hipStream_t st);
 
-// r = rhs - (I + hA (x) K) x; V0 = r; partial norms.  rhs == nullptr with f
-// given means rhs = 1 (x) f.
-void residual_full(const OpView<double> &K, const double *x, const double *hA, int s,
-                   const double *rhs, const double *f, double *V0, double *partial,
-                   hipStream_t st);
+// r = rhs - (I (x) M + hA (x) K) x; V0 = r; partial norms.  rhs == nullptr
+// with f given means rhs = 1 (x) f; M == nullptr means M = I.
+void residual_full(const OpView<double> &K, const OpView<double> *M, const double *x,
+                   const double *hA, int s, const double *rhs, const double *f, double *V0,
+                   double *partial, hipStream_t st);
 
-// y = (I + hA (x) K) x for a double stage-major x (the Kronecker SpMM alone).
-void kron_apply(const OpView<double> &K, const double *x, const double *hA, int s, double *y,
-                hipStream_t st);
+// y = (I (x) M + hA (x) K) x for a double stage-major x (the Kronecker SpMM
+// alone); M == nullptr means M = I.
+void kron_apply(const OpView<double> &K, const OpView<double> *M, const double *x,
+                const double *hA, int s, double *y, hipStream_t st);
 
 // Stage values U_i = u + sum_j hA[i][j] k_j.
 void stage_values(const double *u, const double *k, const double *hA, int s, size_t N, double *U,

@@ -84,6 +84,12 @@ struct irk_solver {
   int lt = 0;  // first level handled by the single-workgroup tail kernel
   std::vector<int> lnx, lny;
 
+  // mass matrix (Sec. 3.1: M_kl = integral of phi_k phi_l); none means M = I
+  bool has_mass = false;
+  Stencil9 Mst;
+  DevOp<double> M64;
+  OpView<double> Mview{};
+
   // operators (rebuilt by irk_update_operator)
   DevOp<double> K64;
   DevOp<float> K32;
@@ -228,17 +234,17 @@ void free_list(std::vector<void *> &list) {
   list.clear();
 }
 
-// Build the operators: K on the fine grid and, for every stage block
-// D_i = I + tau_i K (Sec. 4.2), the Galerkin hierarchy S_l + tau_i K_l and the
+// Build the operators: K (and M) on the fine grid and, for every stage block
+// D_i = M + tau_i K (Sec. 4.2), the Galerkin hierarchy S_l + tau_i K_l and the
 // dense inverse on the coarsest level.
 irk_status build_operators(irk_solver *S, const irk_csr *K) {
   Stencil9 K0;
   if (!irk::csr_to_stencil(K->n, K->rowptr, K->colind, K->val, S->nx, S->ny, K0, S->err))
     return IRK_E_INVALID;
   S->symmetric = irk::is_symmetric(K0, 1e-13);
-  // hierarchy of S_l = R S_{l-1} P (S_0 = I) and K_l = R K_{l-1} P
+  // hierarchy of S_l = R S_{l-1} P (S_0 = M) and K_l = R K_{l-1} P
   std::vector<Stencil9> Sl, Kl;
-  Sl.push_back(irk::identity_stencil(S->nx, S->ny));
+  Sl.push_back(S->has_mass ? S->Mst : irk::identity_stencil(S->nx, S->ny));
   Kl.push_back(K0);
   while ((long long)Sl.back().nx * Sl.back().ny > S->opt.coarse_max && Sl.back().nx % 2 == 0 &&
          Sl.back().ny % 2 == 0 && Sl.back().nx >= 2 && Sl.back().ny >= 2) {
@@ -287,6 +293,12 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   const bool mixed = S->opt.precision == IRK_MIXED;
   const int npt0 = stencil_npt(K0);
   S->K64 = upload_op<double>(S, K0, cm, npt0);
+  if (S->has_mass) {
+    double tmpm[9][9];
+    S->M64 = upload_op<double>(S, S->Mst, irk::classify(S->Mst, 1e-12, tmpm),
+                               stencil_npt(S->Mst));
+    S->Mview = S->M64.view();
+  }
   if (mixed) S->K32 = upload_op<float>(S, K0, cm, npt0);
   for (int i = 0; i < S->s; ++i) {
     for (int l = 0; l + 1 < L; ++l) {
@@ -403,6 +415,9 @@ template <>
 OpView<double> Kview<double>(const irk_solver *S) {
   return S->K64.view();
 }
+
+// The mass operator for the Kronecker products, or nullptr for M = I.
+const OpView<double> *mass(const irk_solver *S) { return S->has_mass ? &S->Mview : nullptr; }
 template <>
 OpView<float> Kview<float>(const irk_solver *S) {
   return S->K32.view();
@@ -556,13 +571,16 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
     const double cbytes = (double)N * (8.0 + es * (ncoup + 1)) +
                           (ncoup ? op_bytes(S, N, S->K64.npt, es) : 0.0);
     const DevOp<T> *D0 = S->lt > 0 ? &Dops<T>(S)[i][0] : nullptr;
+    bool ws9_0 = false;  // FP32 nine-point constant-coefficient finest level (M != I)
+    if constexpr (std::is_same_v<T, float>)
+      ws9_0 = D0 && !split_ok<T>(*D0) && irk::kern::ws9_ok(D0->view(), S->opt.nu_pre);
     if (D0 && split_ok<T>(*D0) && split_ok<T>(Kdev<T>(S))) {
       // streaming coupling pass, then the plain two-columns-per-lane V-cycle
       ProfTok tk = prof_begin(S, IRK_KC_COUPLE, cbytes);
       couple_split<T>(S, v, scale_j, z, C + (size_t)i * S->s, i);
       prof_end(S, tk);
       vcycle<T>(S, i, b0, z + (size_t)i * N, false);
-    } else if (D0) {
+    } else if (D0 && !ws9_0) {
       // coupling fused into the finest-level down pass (+ rc = R(b - D x))
       const DevOp<T> &D = *D0;
       ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,
@@ -647,11 +665,12 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       const double kb = op_bytes(S, N, S->K64.npt, 8);
       const double zb = (double)sN * sizeof(T), vb = (double)sN * 8.0;
       ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb);
-      spmm_dots<T>(K, Z, sys.hA, s, S->V, S->scale, S->ks, j, S->partial, st);
+      spmm_dots<T>(K, mass(S), Z, sys.hA, s, S->V, S->scale, S->ks, j, S->partial, st);
       prof_end(S, t1);
       reduce_cols(S->partial, nblk_pt, S->ks, j, 1, 0, S->h1, st);
       ProfTok t2 = prof_begin(S, IRK_KC_SPMM_UPDATE, zb + vb * (j + 2) + kb);
-      spmm_update<T>(K, Z, sys.hA, s, S->V, S->scale, S->h1, S->ks, S->V, S->pnorm, st);
+      spmm_update<T>(K, mass(S), Z, sys.hA, s, S->V, S->scale, S->h1, S->ks, S->V, S->pnorm,
+                     st);
       prof_end(S, t2);
       // second classical Gram-Schmidt pass, skipped on the device when the
       // first one kept most of ||w|| (reorth = 2) or never run (reorth = 0)
@@ -704,7 +723,8 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     // true residual of the accumulated solution: verifies a converged estimate
     // (single-pass Gram-Schmidt can make the estimate optimistic) or starts
     // the next restart cycle
-    residual_full(K, S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V, S->partial,
+    residual_full(K, mass(S), S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V,
+                  S->partial,
                   st);
     finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
     HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -789,7 +809,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       const double *Vj = S->V + (size_t)j * sN;
       double *Zj = Z + (size_t)j * sN;
       double *Vn = S->V + (size_t)(j + 1) * sN;
-      kron_apply(K, Vj, sys.hA, s, u, st);
+      kron_apply(K, mass(S), Vj, sys.hA, s, u, st);
       apply_precond<double>(S, u, S->scale + j, Zj, sys.C, sys.ord);
       rhs_copy(Zj, sN, Vn, S->partial, st);
       // two classical Gram-Schmidt passes (h1, then h2)
@@ -836,7 +856,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     if (status == IRK_E_BREAKDOWN || (stop && status == IRK_E_NOT_CONVERGED)) break;
     if (status == IRK_OK && !S->opt.true_resid) break;
     // preconditioned residual of the accumulated solution: P^-1 (rhs - A k)
-    residual_full(K, S->acc, sys.hA, s, nullptr, S->f, S->V, S->partial, st);
+    residual_full(K, mass(S), S->acc, sys.hA, s, nullptr, S->f, S->V, S->partial, st);
     apply_precond<double>(S, S->V, S->one, Z, sys.C, sys.ord);
     rhs_copy(Z, sN, S->V, S->partial, st);
     finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
@@ -953,10 +973,6 @@ irk_status irk_setup(irk_solver **out, const irk_butcher *tab, const irk_csr *M,
       S->err = "bad Butcher tableau (need 1 <= s <= 8 and non-null A, b)";
       return IRK_E_INVALID;
     }
-    if (M) {
-      S->err = "only M = I is supported (pass M = NULL)";
-      return IRK_E_INVALID;
-    }
     if (!K || !grid) {
       S->err = "K and the structured grid are required";
       return IRK_E_INVALID;
@@ -980,6 +996,23 @@ irk_status irk_setup(irk_solver **out, const irk_butcher *tab, const irk_csr *M,
     }
     S->N = (size_t)S->nx * S->ny;
     S->sN = S->N * S->s;
+    if (M) {
+      if (M->n != K->n) {
+        S->err = "M and K differ in size";
+        return IRK_E_INVALID;
+      }
+      std::string merr;
+      if (!irk::csr_to_stencil(M->n, M->rowptr, M->colind, M->val, S->nx, S->ny, S->Mst, merr)) {
+        S->err = "M: " + merr;
+        return IRK_E_INVALID;
+      }
+      for (size_t p = 0; p < S->N; ++p)
+        if (!(S->Mst.c[4][p] > 0.0)) {
+          S->err = "M needs a positive diagonal";
+          return IRK_E_INVALID;
+        }
+      S->has_mass = true;
+    }
     S->h = h_t;
     const int s = S->s;
     for (int i = 0; i < s * s; ++i) {
@@ -1103,6 +1136,10 @@ irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *
                             double *lam_n_dev, double *psi_dev, double *U_dev, irk_stats *st) {
   if (!S || !u_n_dev || !lam_np1_dev || !lam_n_dev) return IRK_E_INVALID;
   return guarded(S, [&]() -> irk_status {
+    if (S->has_mass) {
+      S->err = "the adjoint step needs M = I";
+      return IRK_E_INVALID;
+    }
     if (!S->symmetric) {
       S->err = "the adjoint step needs a symmetric K";
       return IRK_E_INVALID;
@@ -1152,7 +1189,7 @@ irk_status irk_grad_diffusion_nodes(irk_solver *S, const double *psi_dev, const 
 irk_status irk_apply_operator(irk_solver *S, const double *x_dev, double *y_dev) {
   if (!S || !x_dev || !y_dev) return IRK_E_INVALID;
   return guarded(S, [&]() -> irk_status {
-    irk::kern::kron_apply(S->K64.view(), x_dev, S->hA, S->s, y_dev, S->stream);
+    irk::kern::kron_apply(S->K64.view(), mass(S), x_dev, S->hA, S->s, y_dev, S->stream);
     HIP_TRY(hipStreamSynchronize(S->stream));
     return IRK_OK;
   });

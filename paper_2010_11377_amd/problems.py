@@ -1,10 +1,11 @@
-"""Finite-difference operators fed to the GPU solver, as CSR arrays.
+"""Spatial operators fed to the GPU solver, as CSR arrays.
 
 The paper's test problems (Sec. 3.1, heat equation (3.1); Sec. 3.2, double
 glazing (3.3)) discretised by finite differences on the ``n x n`` interior
 nodes of a square, boundary nodes eliminated, unknown ``j * n + i`` with x
-fastest, ``M = I`` and ``u' = -K u + g``; plus the variable-coefficient
-diffusion ``u_t = div(kappa grad u)`` used by the adjoint.
+fastest, ``M = I`` and ``u' = -K u + g``; the variable-coefficient diffusion
+``u_t = div(kappa grad u)`` used by the adjoint; and the heat equation with
+linear finite elements, where ``M u' = -K u`` with a consistent mass matrix.
 
 Each builder returns ``(indptr, indices, data)`` with sorted columns (int32,
 int32, float64) and, where the problem has boundary data, the source ``g``.
@@ -13,15 +14,19 @@ import numpy as np
 
 # neighbour order inside a row, by increasing column index: S, W, C, E, N
 _OFFS = [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)]
+# seven-point pattern of linear elements on right triangles whose diagonals
+# run from south-west to north-east: SW, S, W, C, E, N, NE
+_OFFS7 = [(-1, -1), (0, -1), (-1, 0), (0, 0), (1, 0), (0, 1), (1, 1)]
 
 
-def _assemble(n, coef, ny=None):
-    """CSR from five coefficient fields coef[k] (ny x n, indexed [j, i]) for
-    the neighbours in _OFFS; couplings that leave the grid are dropped."""
+def _assemble(n, coef, ny=None, offs=_OFFS):
+    """CSR from coefficient fields coef[k] (ny x n, indexed [j, i]) for the
+    neighbours in offs (sorted by column); couplings that leave the grid are
+    dropped."""
     ny = n if ny is None else ny
     jj, ii = np.meshgrid(np.arange(ny), np.arange(n), indexing="ij")
     present = []
-    for (dx, dy) in _OFFS:
+    for (dx, dy) in offs:
         present.append((ii + dx >= 0) & (ii + dx < n) & (jj + dy >= 0) & (jj + dy < ny))
     counts = np.sum(np.stack(present), axis=0).ravel()
     indptr = np.zeros(n * ny + 1, dtype=np.int64)
@@ -31,7 +36,7 @@ def _assemble(n, coef, ny=None):
     data = np.empty(nnz, dtype=np.float64)
     pos = indptr[:-1].copy()
     row = (jj * n + ii).ravel()
-    for k, (dx, dy) in enumerate(_OFFS):
+    for k, (dx, dy) in enumerate(offs):
         m = present[k].ravel()
         r = row[m]
         indices[pos[m]] = (r + dy * n + dx).astype(np.int32)
@@ -95,3 +100,22 @@ def to_dense(indptr, indices, data, n):
         for e in range(indptr[r], indptr[r + 1]):
             A[r, indices[e]] += data[e]
     return A
+
+
+def p1_heat(n, length=1.0):
+    """Heat equation with continuous piecewise-linear elements on the uniform
+    triangulation of a square of side ``length`` (n x n interior nodes,
+    spacing h = length/(n+1), every cell cut by its south-west to north-east
+    diagonal), homogeneous Dirichlet data: returns ``(M, K)`` as CSR triples.
+
+    On this mesh the stiffness matrix is the five-point stencil
+    ``(4, -1, -1, -1, -1)`` (the couplings along the diagonals cancel) and the
+    consistent mass matrix has ``h^2 / 2`` on the diagonal and ``h^2 / 12`` for
+    each of the six neighbours joined by an edge (W, E, S, N, SW, NE)."""
+    h = length / (n + 1)
+    one = np.ones((n, n))
+    K = _assemble(n, [-one, -one, 4.0 * one, -one, -one])
+    e = h * h / 12.0
+    M = _assemble(n, [e * one, e * one, e * one, 6.0 * e * one, e * one, e * one, e * one],
+                  offs=_OFFS7)
+    return M, K

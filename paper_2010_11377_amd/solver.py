@@ -38,12 +38,13 @@ class IRKSolver:
     AMG V-cycle per stage block.
 
     Parameters: Butcher ``(A, b, c)``; ``K`` as CSR ``(indptr, indices, data)``
-    on the ``grid = (nx, ny)``; timestep ``h_t``; options of ``irk_options``.
+    on the ``grid = (nx, ny)``; timestep ``h_t``; options of ``irk_options``;
+    ``M`` the mass matrix as CSR on the same grid (None: ``M = I``).
     """
 
     def __init__(self, A, b, c, K, h_t, grid, precision="fp64", precond="LD", restart=40,
                  max_iter=200, nu_pre=2, nu_post=2, coarse_max=64, rtol=1e-8, true_resid=True,
-                 reorth=0, side="right", device=None):
+                 reorth=0, side="right", M=None, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("IRKSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = B.lib()
@@ -70,12 +71,17 @@ class IRKSolver:
         self.options = opt
         tab = B.Butcher(self.s, B.dptr(self.A), B.dptr(self._b), B.dptr(self._c))
         csr, keep = _csr_struct(*K)
+        mcsr = None
+        if M is not None:
+            mcsr, mkeep = _csr_struct(*M)
         g = B.Grid(self.nx, self.ny)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device)
             self._stream = stream
-            st = self.lib.irk_setup(ctypes.byref(handle), ctypes.byref(tab), None, ctypes.byref(csr),
+            st = self.lib.irk_setup(ctypes.byref(handle), ctypes.byref(tab),
+                                    ctypes.byref(mcsr) if mcsr is not None else None,
+                                    ctypes.byref(csr),
                                     self.h_t, ctypes.byref(g), ctypes.byref(opt),
                                     ctypes.c_void_p(stream.cuda_stream))
         if st != B.IRK_OK:

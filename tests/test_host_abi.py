@@ -131,9 +131,25 @@ def test_setup_validation_before_any_device_work():
     d2[3] = np.nan
     st, msg, _ = _setup_status(A, b, (K[0], K[1], d2), 0.01, (n, n))
     assert st == B.IRK_E_INVALID and "finite" in msg
-    # M other than the identity
+    # mass matrices: wrong size, a coupling outside the 3 x 3 neighbourhood,
+    # a zero diagonal entry
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), M=B.CSR())
-    assert st == B.IRK_E_INVALID and "M = I" in msg
+    assert st == B.IRK_E_INVALID and "M and K differ" in msg
+    from paper_2010_11377_amd.solver import _csr_struct
+    mp, mi, md = problems.p1_heat(n)[0]
+    far = mi.copy()
+    far[mp[10] + 1] = (far[mp[10] + 1] + 3 * n) % (n * n)
+    far_sorted = far.copy()
+    for r in range(n * n):
+        far_sorted[mp[r]:mp[r + 1]] = np.sort(far[mp[r]:mp[r + 1]])
+    mcsr, keep = _csr_struct(mp, far_sorted, md)
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), M=mcsr)
+    assert st == B.IRK_E_INVALID and msg.startswith("M:")
+    zd = md.copy()
+    zd[mp[10] + 3] = 0.0                 # row 10 (i = 2, j = 1): SW, S, W, C
+    mcsr2, keep2 = _csr_struct(mp, mi, zd)
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), M=mcsr2)
+    assert st == B.IRK_E_INVALID and "diagonal" in msg
 
 
 # ---------------------------------------------------------------- host library
