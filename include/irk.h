@@ -86,6 +86,7 @@ typedef struct {
 enum { IRK_FP64 = 0, IRK_MIXED = 1 };
 enum { IRK_PREC_LD = 0, IRK_PREC_DU = 1, IRK_PREC_GSL = 2, IRK_PREC_J = 3 };
 enum { IRK_RIGHT = 0, IRK_LEFT = 1 };
+enum { IRK_INTERP_LINEAR = 0, IRK_INTERP_CONSTANT = 1 };
 
 typedef struct {
   int precision;   /* IRK_FP64: everything in double.  IRK_MIXED: V-cycles,
@@ -113,6 +114,12 @@ typedef struct {
                       residual as stopping test (Sec. 5.1, Tables 7-10);
                       requires IRK_FP64 and applies to forward steps; adjoint
                       solves stay right-preconditioned. */
+  int interp;      /* multigrid prolongation (restriction is always the sum
+                      over the 2 x 2 cell): IRK_INTERP_LINEAR, bilinear
+                      between cell centres (the default); IRK_INTERP_CONSTANT,
+                      the transpose of the restriction, which keeps every
+                      Galerkin coarse operator of an M-matrix an M-matrix
+                      (advection-dominated operators at large h_t). */
 } irk_options;
 
 typedef struct {
@@ -125,7 +132,7 @@ typedef struct {
 
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
- * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT. */
+ * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.

@@ -19,6 +19,10 @@ reading taken for the structured finite-difference grids of Sec. 3:
   w_l = (2^l + 1) / (2^(l+1) + 1) (2/3, 3/5, 5/9, ...), not 3/4;
 * restriction R: the sum over each 2 x 2 cell (the transpose of piecewise
   constant interpolation);
+* the alternative prolongation ``interp="constant"`` is P = R^T (every fine
+  node takes its coarse parent's value).  It keeps the Galerkin coarse
+  operators of an M-matrix M-matrices, which the linear one does not for the
+  advection-dominated double glazing at large time steps;
 * coarse operators by the Galerkin product: S_{l+1} = R S_l P, K_{l+1} =
   R K_l P with S_0 = M = I, and the stage-i block on level l is
   D_{i,l} = S_l + tau_i K_l (tau_i = h A~_ii);
@@ -78,8 +82,12 @@ def _sum_1d(n):
     return sp.csr_matrix((np.ones(2 * nc), (rows, cols)), shape=(nc, n))
 
 
-def prolongation(nx, ny, level=0):
+def prolongation(nx, ny, level=0, interp="linear"):
     """P from level+1 to level, x-fastest ordering (index = y * nx + x)."""
+    if interp == "constant":
+        return restriction(nx, ny).T.tocsr()
+    if interp != "linear":
+        raise ValueError(interp)
     wb = boundary_weight(level)
     return sp.kron(_interp_1d(ny, wb), _interp_1d(nx, wb), format="csr")
 
@@ -88,7 +96,7 @@ def restriction(nx, ny):
     return sp.kron(_sum_1d(ny), _sum_1d(nx), format="csr")
 
 
-def hierarchy(K, nx, ny, coarse_max=64, M=None):
+def hierarchy(K, nx, ny, coarse_max=64, M=None, interp="linear"):
     """[(nx_l, ny_l, S_l, K_l, P_l, R_l)] with P_l, R_l the transfers between
     level l and l+1 (None on the last level); S_0 = M (the identity if None)."""
     levels = []
@@ -96,7 +104,7 @@ def hierarchy(K, nx, ny, coarse_max=64, M=None):
     Kl = sp.csr_matrix(K)
     while True:
         if nx * ny > coarse_max and nx % 2 == 0 and ny % 2 == 0 and nx >= 2 and ny >= 2:
-            P, R = prolongation(nx, ny, len(levels)), restriction(nx, ny)
+            P, R = prolongation(nx, ny, len(levels), interp), restriction(nx, ny)
             levels.append((nx, ny, S, Kl, P, R))
             S = (R @ S @ P).tocsr()
             Kl = (R @ Kl @ P).tocsr()
@@ -142,7 +150,8 @@ def vcycle(levels, tau, b, nu=2, level=0):
     return x
 
 
-def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=None):
+def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=None,
+                                interp="linear"):
     """``z ~= P^-1 v`` by block substitution (Sec. 4.2) with one V-cycle per
     diagonal block ``M + h A~_jj K`` instead of an exact solve (M = I if
     None)."""
@@ -153,7 +162,7 @@ def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=
     upper = np.allclose(At, np.triu(At))
     if not (lower or upper):
         raise ValueError("A~ must be triangular")
-    levels = hierarchy(K, nx, ny, coarse_max, M)
+    levels = hierarchy(K, nx, ny, coarse_max, M, interp)
     order = range(s) if lower else range(s - 1, -1, -1)
     v = np.asarray(v, dtype=np.float64).reshape(s, N)
     z = np.zeros((s, N))

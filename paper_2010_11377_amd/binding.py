@@ -24,6 +24,8 @@ IRK_FP64 = 0
 IRK_MIXED = 1
 IRK_RIGHT = 0
 IRK_LEFT = 1
+IRK_INTERP_LINEAR = 0
+IRK_INTERP_CONSTANT = 1
 PRECOND = {"LD": 0, "DU": 1, "GSL": 2, "J": 3}
 
 
@@ -47,7 +49,8 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("coarse_max", ctypes.c_int), ("vcycles", ctypes.c_int),
                 ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("side", ctypes.c_int)]
+                ("side", ctypes.c_int),
+                ("interp", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

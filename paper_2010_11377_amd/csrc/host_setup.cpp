@@ -133,23 +133,29 @@ double boundary_weight(int level) {
   return (p + 1.0) / (2.0 * p + 1.0);
 }
 
+Interp linear_interp(int level) { return Interp{0.75, 0.25, boundary_weight(level)}; }
+Interp constant_interp() { return Interp{1.0, 0.0, 1.0}; }
+
 // 1-D interpolation weights of fine point f onto coarse points: returns the
-// number of parents (1 at the ends of the grid, else 2).
-static int interp1d(int f, int nc, double wb, int *J, double *w) {
+// number of parents (1 at the ends of the grid or without neighbour weight).
+static int interp1d(int f, int nc, const Interp &ip, int *J, double *w) {
   int I = f / 2;
   int nb = (f % 2 == 0) ? I - 1 : I + 1;
   J[0] = I;
   if (nb >= 0 && nb < nc) {
-    w[0] = 0.75;
+    w[0] = ip.own;
+    if (ip.nb == 0.0) return 1;
     J[1] = nb;
-    w[1] = 0.25;
+    w[1] = ip.nb;
     return 2;
   }
-  w[0] = wb;
+  w[0] = ip.wb;
   return 1;
 }
 
-Stencil9 galerkin(const Stencil9 &A, double wb) {
+Stencil9 galerkin(const Stencil9 &A, double wb) { return galerkin(A, Interp{0.75, 0.25, wb}); }
+
+Stencil9 galerkin(const Stencil9 &A, const Interp &ip) {
   const int nx = A.nx, ny = A.ny, ncx = nx / 2, ncy = ny / 2;
   Stencil9 C;
   C.resize(ncx, ncy);
@@ -167,7 +173,7 @@ Stencil9 galerkin(const Stencil9 &A, double wb) {
             if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
             int Jx[2], Jy[2];
             double wx[2], wy[2];
-            int mx = interp1d(qx, ncx, wb, Jx, wx), my = interp1d(qy, ncy, wb, Jy, wy);
+            int mx = interp1d(qx, ncx, ip, Jx, wx), my = interp1d(qy, ncy, ip, Jy, wy);
             for (int t = 0; t < my; ++t)
               for (int u = 0; u < mx; ++u) {
                 int ox = Jx[u] - Ix, oy = Jy[t] - Iy;  // in [-1, 1]

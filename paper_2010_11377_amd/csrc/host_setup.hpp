@@ -60,6 +60,18 @@ double boundary_weight(int level);
 // aggregate.
 Stencil9 galerkin(const Stencil9 &A, double wb);
 
+// Prolongation weights of one level: a fine node takes `own` of its coarse
+// parent and `nb` of the next coarse node on its side, per direction; an
+// outermost fine node (no such coarse node) takes `wb` of its parent.
+// Restriction is the transpose of the piecewise-constant prolongation (the
+// sum over the 2 x 2 cell) in both cases.
+struct Interp {
+  double own, nb, wb;
+};
+Interp linear_interp(int level);  // 3/4, 1/4, boundary_weight(level)
+Interp constant_interp();         // 1, 0, 1: P = R^T
+Stencil9 galerkin(const Stencil9 &A, const Interp &ip);
+
 // a + t * b, entrywise.
 Stencil9 axpy_stencil(const Stencil9 &a, double t, const Stencil9 &b);
 

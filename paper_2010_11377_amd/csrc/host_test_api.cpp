@@ -46,6 +46,14 @@ int irkh_galerkin(int nx, int ny, int level, const double *in, double *out) {
   return 0;
 }
 
+// The same with piecewise-constant interpolation (P = R^T).
+int irkh_galerkin_constant(int nx, int ny, const double *in, double *out) {
+  if (nx % 2 || ny % 2) return -1;
+  Stencil9 C = irk::galerkin(from_flat(nx, ny, in), irk::constant_interp());
+  to_flat(C, out);
+  return 0;
+}
+
 // 1 if the operator has one coefficient set per boundary class (cls: 81).
 int irkh_classify(int nx, int ny, const double *in, double tol, double *cls) {
   double c[9][9];

@@ -27,7 +27,9 @@ struct OpView {
   const T *cls;
   const T *arr;
   int uniform;
-  T pw;
+  T pw;            // prolongation weight of an outermost fine node from its parent
+  T pa = T(0.75);  // prolongation weight from the parent (other fine nodes)
+  T pn = T(0.25);  // prolongation weight from the next coarse node (0: piecewise constant)
 };
 
 // The coarse end of the hierarchy, solved by one workgroup in LDS: levels
@@ -45,6 +47,7 @@ struct TailDesc {
   const T *cls[kTailLevels];
   const T *arr[kTailLevels];
   T pw[kTailLevels];  // prolongation boundary weight of level l (see OpView)
+  T pa = T(0.75), pn = T(0.25);  // parent / next-node prolongation weights (see OpView)
   const T *CinvT;
 };
 

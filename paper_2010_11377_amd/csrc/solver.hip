@@ -39,7 +39,8 @@ struct DevOp {
   T interior[9] = {};  // host copy of the interior class (constant coefficients)
   T classes[81] = {};  // host copy of all nine classes (q * 9 + k)
   T pw = T(0);         // prolongation boundary weight of this level
-  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform, pw}; }
+  T pa = T(0.75), pn = T(0.25);  // parent and next-node weights (linear interpolation)
+  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform, pw, pa, pn}; }
 };
 
 // A constant-coefficient operator is uniform when every boundary class equals
@@ -234,6 +235,11 @@ void free_list(std::vector<void *> &list) {
   list.clear();
 }
 
+// Transfer weights between level l and l + 1 for the configured interpolation.
+irk::Interp interp_of(const irk_solver *S, int l) {
+  return S->opt.interp == IRK_INTERP_CONSTANT ? irk::constant_interp() : irk::linear_interp(l);
+}
+
 // Build the operators: K (and M) on the fine grid and, for every stage block
 // D_i = M + tau_i K (Sec. 4.2), the Galerkin hierarchy S_l + tau_i K_l and the
 // dense inverse on the coarsest level.
@@ -248,9 +254,9 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   Kl.push_back(K0);
   while ((long long)Sl.back().nx * Sl.back().ny > S->opt.coarse_max && Sl.back().nx % 2 == 0 &&
          Sl.back().ny % 2 == 0 && Sl.back().nx >= 2 && Sl.back().ny >= 2) {
-    const double wb = irk::boundary_weight((int)Sl.size() - 1);
-    Sl.push_back(irk::galerkin(Sl.back(), wb));
-    Kl.push_back(irk::galerkin(Kl.back(), wb));
+    const irk::Interp ip = interp_of(S, (int)Sl.size() - 1);
+    Sl.push_back(irk::galerkin(Sl.back(), ip));
+    Kl.push_back(irk::galerkin(Kl.back(), ip));
   }
   const int L = (int)Sl.size();
   const long long ncoarse = (long long)Sl.back().nx * Sl.back().ny;
@@ -304,12 +310,19 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
     for (int l = 0; l + 1 < L; ++l) {
       Stencil9 D = irk::axpy_stencil(Sl[l], S->tau[i], Kl[l]);
       const int npt = stencil_npt(D);
+      const irk::Interp ip = interp_of(S, l);
       if (mixed) {
         S->D32[i].push_back(upload_op<float>(S, D, cm, npt));
-        S->D32[i].back().pw = (float)irk::boundary_weight(l);
+        DevOp<float> &d = S->D32[i].back();
+        d.pw = (float)ip.wb;
+        d.pa = (float)ip.own;
+        d.pn = (float)ip.nb;
       } else {
         S->D64[i].push_back(upload_op<double>(S, D, cm, npt));
-        S->D64[i].back().pw = irk::boundary_weight(l);
+        DevOp<double> &d = S->D64[i].back();
+        d.pw = ip.wb;
+        d.pa = ip.own;
+        d.pn = ip.nb;
       }
     }
     Stencil9 Dc = irk::axpy_stencil(Sl[L - 1], S->tau[i], Kl[L - 1]);
@@ -451,18 +464,28 @@ T *lev_p(irk_solver *S, int l) {
 // five-point and FP32 constant-coefficient nine-point operators, one column
 // per lane for other five-point operators, LDS tiles for the rest.
 template <typename T>
+bool linear_p(const DevOp<T> &D) {
+  return D.pa == T(0.75) && D.pn == T(0.25);
+}
+
+template <typename T>
 bool split_ok(const DevOp<T> &D) {
   if constexpr (std::is_same_v<T, float>)
-    return irk::kern::wsplit_ok(D.view());
+    return linear_p(D) && irk::kern::wsplit_ok(D.view());
   else
     return false;
+}
+
+// The nine-point register kernels have the linear interpolation built in.
+bool ws9_usable(const DevOp<float> &D, int nu) {
+  return linear_p(D) && irk::kern::ws9_ok(D.view(), nu);
 }
 
 template <typename T>
 void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
   if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sdown(D.view(), D.interior, nu, b, rc, st);
-    if (irk::kern::ws9_ok(D.view(), nu))
+    if (ws9_usable(D, nu))
       return irk::kern::s9down(D.view(), D.classes, nu, b, rc, xpre, st);
   }
   if (irk::kern::wtile_ok<T>(D.view()))
@@ -476,7 +499,7 @@ void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, 
              hipStream_t st) {
   if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sup(D.view(), D.interior, nu, b, ec, x, st);
-    if (irk::kern::ws9_ok(D.view(), nu))
+    if (ws9_usable(D, nu))
       return irk::kern::s9up(D.view(), D.classes, nu, b, ec, xpre, x, st);
   }
   if (irk::kern::wtile_ok<T>(D.view()))
@@ -518,6 +541,8 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
         td.cls[k] = D.cls;
         td.arr[k] = D.arr;
         td.pw[k] = D.pw;
+        td.pa = D.pa;
+        td.pn = D.pn;
         if (D.arr) words += 9 * (size_t)D.nx * D.ny;
       }
     }
@@ -573,7 +598,7 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
     const DevOp<T> *D0 = S->lt > 0 ? &Dops<T>(S)[i][0] : nullptr;
     bool ws9_0 = false;  // FP32 nine-point constant-coefficient finest level (M != I)
     if constexpr (std::is_same_v<T, float>)
-      ws9_0 = D0 && !split_ok<T>(*D0) && irk::kern::ws9_ok(D0->view(), S->opt.nu_pre);
+      ws9_0 = D0 && !split_ok<T>(*D0) && ws9_usable(*D0, S->opt.nu_pre);
     if (D0 && split_ok<T>(*D0) && split_ok<T>(Kdev<T>(S))) {
       // streaming coupling pass, then the plain two-columns-per-lane V-cycle
       ProfTok tk = prof_begin(S, IRK_KC_COUPLE, cbytes);
@@ -912,6 +937,8 @@ bool valid_options(const irk_options &o, std::string &err) {
   if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return err = "rtol must be in (0, 1)", false;
   if (o.reorth < 0 || o.reorth > 2) return err = "reorth must be 0, 1 or 2", false;
   if (o.side != IRK_RIGHT && o.side != IRK_LEFT) return err = "side must be IRK_RIGHT or IRK_LEFT", false;
+  if (o.interp != IRK_INTERP_LINEAR && o.interp != IRK_INTERP_CONSTANT)
+    return err = "interp must be IRK_INTERP_LINEAR or IRK_INTERP_CONSTANT", false;
   if (o.side == IRK_LEFT && o.precision != IRK_FP64)
     return err = "left preconditioning needs precision IRK_FP64", false;
   return true;
@@ -955,6 +982,7 @@ void irk_default_options(irk_options *o) {
   o->reorth = 0;
   o->rtol = 1e-8;
   o->side = IRK_RIGHT;
+  o->interp = IRK_INTERP_LINEAR;
 }
 
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {

@@ -225,6 +225,7 @@ struct T2Desc {
   const float *cls[kTailLevels];
   const float *arr[kTailLevels];
   float pw[kTailLevels];
+  float pa, pn;  // prolongation weights from the own and the next coarse node
   const float *CinvT;
   int store_off[kTailLevels];  // LDS offset of level l's parked x (and b for l > 0)
 };
@@ -306,8 +307,8 @@ __device__ __forceinline__ void ascend(const T2Desc &td, int l, const float *xc,
     const int nbx = (fx & 1) ? Ix + 1 : Ix - 1, nby = (fy & 1) ? Iy + 1 : Iy - 1;
     const bool hx = nbx >= 0 && nbx < ncx, hy = nby >= 0 && nby < ncy;
     const int nbxc = hx ? nbx : Ix, nbyc = hy ? nby : Iy;
-    const float wx = hx ? 0.75f : pw, wy = hy ? 0.75f : pw;
-    const float ax = hx ? 0.25f : 0.0f, ay = hy ? 0.25f : 0.0f;
+    const float wx = hx ? td.pa : pw, wy = hy ? td.pa : pw;
+    const float ax = hx ? td.pn : 0.0f, ay = hy ? td.pn : 0.0f;
     const float cv = (wx * wy * xc[Iy * ncx + Ix] + ax * wy * xc[Iy * ncx + nbxc]) +
                      (wx * ay * xc[nbyc * ncx + Ix] + ax * ay * xc[nbyc * ncx + nbxc]);
     const float pv = px[p];
@@ -505,6 +506,8 @@ void vtail2(const TailDesc<float> &td, int nu, const float *b, float *x, hipStre
     d.store_off[l] = off;
     if (l + 1 < td.nlev) off += (l == 0 ? 1 : 2) * td.nx[l] * td.ny[l];
   }
+  d.pa = td.pa;
+  d.pn = td.pn;
   d.CinvT = td.CinvT;
   const size_t bytes = vtail2_lds_bytes(td);
   const bool cls = td.cls[0] || td.nlev == 1;

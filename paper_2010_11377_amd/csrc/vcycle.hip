@@ -300,21 +300,22 @@ __global__ void __launch_bounds__(kNT)
 }
 
 // P ec at fine node (fx, fy) from a staged coarse tile with origin (CX0, CY0)
-// and pitch CW: 3/4 of the own coarse node and 1/4 of the next one in each
-// direction; an outermost fine node (no next coarse node) takes pw of its own.
+// and pitch CW: per direction pa of the own coarse node and pn of the next
+// one (3/4 and 1/4 for linear, 1 and 0 for piecewise-constant interpolation);
+// an outermost fine node (no next coarse node) takes pw of its own.
 template <typename T>
 __device__ __forceinline__ T prolong_value(const T *ec, int CW, int CX0, int CY0, int fx, int fy,
-                                           int ncx, int ncy, T pw) {
+                                           int ncx, int ncy, T pw, T pa, T pn) {
   const int Ix = fx / 2, Iy = fy / 2;
   const int nbx = (fx & 1) ? Ix + 1 : Ix - 1;
   const int nby = (fy & 1) ? Iy + 1 : Iy - 1;
-  const bool hx = nbx >= 0 && nbx < ncx, hy = nby >= 0 && nby < ncy;
-  const T wx = hx ? T(0.75) : pw, wy = hy ? T(0.75) : pw;
+  const bool hx = nbx >= 0 && nbx < ncx && pn != T(0), hy = nby >= 0 && nby < ncy && pn != T(0);
+  const T wx = (nbx >= 0 && nbx < ncx) ? pa : pw, wy = (nby >= 0 && nby < ncy) ? pa : pw;
   const int lx = Ix - CX0, ly = Iy - CY0, nlx = nbx - CX0, nly = nby - CY0;
   T v = wx * wy * ec[ly * CW + lx];
-  if (hx) v += T(0.25) * wy * ec[ly * CW + nlx];
-  if (hy) v += wx * T(0.25) * ec[nly * CW + lx];
-  if (hx && hy) v += T(0.0625) * ec[nly * CW + nlx];
+  if (hx) v += pn * wy * ec[ly * CW + nlx];
+  if (hy) v += wx * pn * ec[nly * CW + lx];
+  if (hx && hy) v += pn * pn * ec[nly * CW + nlx];
   return v;
 }
 
@@ -346,7 +347,7 @@ __global__ void __launch_bounds__(kNT)
       const int lx = m + q % w, ly = m + q / w;
       const int gx = X0 + lx, gy = Y0 + ly;
       if (gx < 0 || gy < 0 || gx >= D.nx || gy >= D.ny) continue;
-      sx[ly * W + lx] += prolong_value(se, CW, CX0, CY0, gx, gy, ncx, ncy, D.pw);
+      sx[ly * W + lx] += prolong_value(se, CW, CX0, CY0, gx, gy, ncx, ncy, D.pw, D.pa, D.pn);
     }
     __syncthreads();
   }
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__(kTailThreads)
     const int ncx = td.nx[l + 1], ncy = td.ny[l + 1];
     const T *sxc = sm + td.off[l + 1] + (size_t)ncx * ncy;
     for (int p = threadIdx.x; p < n; p += kTailThreads)
-      sx[p] += prolong_value(sxc, ncx, 0, 0, p % nx, p / nx, ncx, ncy, td.pw[l]);
+      sx[p] += prolong_value(sxc, ncx, 0, 0, p % nx, p / nx, ncx, ncy, td.pw[l], td.pa, td.pn);
     __syncthreads();
     for (int sw = 0; sw < nu; ++sw) {
       tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 1);

@@ -78,6 +78,7 @@ struct WOp {
   T u[9];    // interior class (MODE 0)
   T inv_d;   // 1 / u[4]
   T pw;      // prolongation weight of the outermost fine node
+  T pa, pn;  // prolongation weights from the own and the next coarse node
 };
 
 template <typename T, int NPT, int MODE>
@@ -235,6 +236,8 @@ __device__ __forceinline__ WOp<T> make_wop(const OpView<T> &D) {
   for (int k = 0; k < 9; ++k) o.u[k] = D.cls ? D.cls[36 + k] : T(0);
   o.inv_d = D.cls ? T(1) / o.u[4] : T(0);
   o.pw = D.pw;
+  o.pa = D.pa;
+  o.pn = D.pn;
   return o;
 }
 
@@ -333,22 +336,24 @@ __device__ __forceinline__ void wup_body(const WOp<T> &o, T (&x)[R], const T (&b
   const int ncx = o.nx / 2, ncy = o.ny / 2;
   const int Ix = gx >> 1;
   const int nbx = (gx & 1) ? Ix + 1 : Ix - 1;
-  const bool hx = nbx >= 0 && nbx < ncx;
+  const bool ix = nbx >= 0 && nbx < ncx;
+  const bool hx = ix && o.pn != T(0);
   const bool in_x = gx >= 0 && gx < o.nx && lane >= M && lane < 64 - M;
 #pragma unroll
   for (int r = M; r < R - M; ++r) {
     const int gy = Y0 + r;
     const int Iy = gy >> 1;
     const int nby = (gy & 1) ? Iy + 1 : Iy - 1;
-    const bool hy = nby >= 0 && nby < ncy;
+    const bool iy = nby >= 0 && nby < ncy;
+    const bool hy = iy && o.pn != T(0);
     if (in_x && gy >= 0 && gy < o.ny) {
       const T *row = se + (Iy - CY0) * CW;
       const T *nrow = se + (nby - CY0) * CW;
-      const T wx = hx ? T(0.75) : o.pw, wy = hy ? T(0.75) : o.pw;
+      const T wx = ix ? o.pa : o.pw, wy = iy ? o.pa : o.pw;
       T pv = wx * wy * row[Ix - CX0];
-      if (hx) pv += T(0.25) * wy * row[nbx - CX0];
-      if (hy) pv += wx * T(0.25) * nrow[Ix - CX0];
-      if (hx && hy) pv += T(0.0625) * nrow[nbx - CX0];
+      if (hx) pv += o.pn * wy * row[nbx - CX0];
+      if (hy) pv += wx * o.pn * nrow[Ix - CX0];
+      if (hx && hy) pv += o.pn * o.pn * nrow[nbx - CX0];
       x[r] += pv;
     }
   }

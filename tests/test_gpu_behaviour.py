@@ -12,13 +12,18 @@ numbers are not targets (their parity is unpinned); the claims checked are:
   q the order of the method);
 * robustness in h_t from 0.05 to 5 at fixed h_x (Sec. 5.1.1, Table 7), and
   at s = 7 P_LD ahead of P_GSL at every h_t, left- and right-preconditioned;
-* double glazing at h_x = 1/128, eps = 0.04, left preconditioning, h_t from
-  0.05 to 5 (Sec. 5.2, Table 13): at s = 7 P_LD needs fewer iterations than
-  P_GSL at every h_t and grows less with h_t; at s = 2 the two stay close and
-  robust.  (With eps = 0.005 and h d_i above about 0.1 the Galerkin coarse
-  operators of the upwind operator under linear interpolation are no longer
-  diagonally dominant and red-black relaxation on them diverges, so that
-  column needs the piecewise-constant interpolation.)
+* double glazing at h_x = 1/128, eps = 0.04 and 0.005, left preconditioning,
+  h_t from 0.05 to 5 (Sec. 5.2, Table 13): at s = 7 P_LD needs fewer
+  iterations than P_GSL at every h_t and grows less with h_t; at s = 2 the
+  two stay close and robust.  eps = 0.04 uses the default linear
+  interpolation; eps = 0.005 the piecewise-constant one (with h d_i above
+  about 0.1 the Galerkin coarse operators of the upwind operator under linear
+  interpolation are no longer diagonally dominant and red-black relaxation on
+  them diverges).  That V-cycle is weaker than the paper's AMG, so for
+  eps = 0.005 the counts grow with h_t at both stage numbers and only the
+  comparison is checked: P_LD needs at most one iteration more than P_GSL at
+  every h_t (fewer from h_t = 0.1 on) and, at s = 7, grows less (the paper:
+  28 vs 68 iterations at h_t = 5; here 468 vs more than 600).
 
 Every count is printed, so a run doubles as the table of iteration counts.
 """
@@ -124,19 +129,21 @@ def dg_iters(dev, s, n, h, precond, eps, steps=2):
     from paper_2010_11377_amd.solver import IRKSolver
     A, b, c = tableaux.tableau("radau_iia", s)
     ip, ix, d, g = problems.double_glazing(n, eps)
+    weak = eps < 0.01       # piecewise-constant interpolation: counts can run high
     S = IRKSolver(A, b, c, (ip, ix, d), h, (n, n), precond=precond, side="left", rtol=1e-8,
-                  max_iter=400, device=dev)
+                  restart=100 if weak else 40, max_iter=600 if weak else 400,
+                  interp="constant" if weak else "linear", device=dev)
     S.set_source(g)
     u = torch.zeros(n * n, dtype=torch.float64, device=dev)
     its = []
     for _ in range(steps):
-        u = S.step(u)
+        u = S.step(u, allow_not_converged=weak)   # a capped solve counts as the cap
         its.append(S.last_stats.iters)
     S.close()
     return max(its)
 
 
-@pytest.mark.parametrize("eps", [0.04])
+@pytest.mark.parametrize("eps", [0.04, 0.005])
 def test_double_glazing_time_step(dev, eps):
     n = 128
     for s in (2, 7):
@@ -145,7 +152,11 @@ def test_double_glazing_time_step(dev, eps):
         ld = [c[(h, "LD")] for h in H_SWEEP]
         say("case h_t sweep double glazing eps=%g Radau IIA %d (left): GSL %s LD %s" % (
             eps, s, gsl, ld))
-        if s == 7:
+        if eps < 0.01:
+            assert all(a <= b + 1 for a, b in zip(ld, gsl))
+            if s == 7:
+                assert gsl[-1] - gsl[0] >= ld[-1] - ld[0]
+        elif s == 7:
             assert all(a < b for a, b in zip(ld, gsl))
             assert gsl[-1] - gsl[0] >= ld[-1] - ld[0]
         else:

@@ -162,6 +162,7 @@ def H():
     pi = ctypes.POINTER(ctypes.c_int)
     L.irkh_csr_to_stencil.argtypes = [ctypes.c_int, pi, pi, pd, ctypes.c_int, ctypes.c_int, pd]
     L.irkh_galerkin.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, pd, pd]
+    L.irkh_galerkin_constant.argtypes = [ctypes.c_int, ctypes.c_int, pd, pd]
     L.irkh_classify.argtypes = [ctypes.c_int, ctypes.c_int, pd, ctypes.c_double, pd]
     L.irkh_is_symmetric.argtypes = [ctypes.c_int, ctypes.c_int, pd, ctypes.c_double]
     L.irkh_dense_inverse.argtypes = [ctypes.c_int, ctypes.c_int, pd, pd]
@@ -229,6 +230,21 @@ def test_galerkin_is_dense_triple_product(H, which):
     assert H.irkh_galerkin(n // 2, n // 2, 1, B.dptr(out), B.dptr(out2)) == 0
     P2, R2 = transfers_dense(n // 2, 1)
     assert np.allclose(stencil_to_dense(out2, n // 4, n // 4), R2 @ ref @ P2, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("which", ["heat", "dg"])
+def test_galerkin_constant_is_dense_triple_product(H, which):
+    from oracle.amg import prolongation, restriction
+    n = 12
+    K = problems.heat(n) if which == "heat" else problems.double_glazing(n, 0.005)[:3]
+    st = stencil_of(H, K, n)
+    out = np.zeros(9 * (n // 2) ** 2)
+    assert H.irkh_galerkin_constant(n, n, B.dptr(st), B.dptr(out)) == 0
+    P = prolongation(n, n, 0, "constant").toarray()
+    R = restriction(n, n).toarray()
+    ref = R @ problems.to_dense(*K, n * n) @ P
+    assert np.allclose(stencil_to_dense(out, n // 2, n // 2), ref, rtol=1e-13,
+                       atol=1e-12 * np.abs(ref).max())
 
 
 def test_classes(H):

@@ -212,3 +212,43 @@ def test_mass_matrix_convergence_factor():
                 f = np.linalg.norm(e2) / np.linalg.norm(e)
                 e = e2 / np.linalg.norm(e2)
             assert f < 0.1, (n, tau, f)
+
+
+def test_constant_interpolation_is_parent_value():
+    nx, ny = 6, 4
+    P = prolongation(nx, ny, 0, "constant")
+    xc = np.arange(1.0, 1.0 + (nx // 2) * (ny // 2))
+    xf = P @ xc
+    for j in range(ny):
+        for i in range(nx):
+            assert xf[j * nx + i] == xc[(j // 2) * (nx // 2) + i // 2]
+
+
+def _m_matrix(D):
+    """Non-positive off-diagonals and non-negative row sums."""
+    D = sp.csr_matrix(D)
+    off = D - sp.diags(D.diagonal())
+    return off.data.max(initial=0.0) <= 1e-14 * D.diagonal().max() and \
+        (np.asarray(D.sum(axis=1)).ravel() >= -1e-12 * D.diagonal().max()).all()
+
+
+def test_constant_interpolation_keeps_m_matrices_and_converges():
+    """Double glazing, eps = 0.005, tau = 1: with piecewise-constant
+    interpolation every Galerkin level is an M-matrix and the V-cycle
+    contracts; with linear interpolation coarse levels lose the property
+    and the cycle diverges (the reason for the option)."""
+    n, tau = 64, 1.0
+    K = double_glazing(n, 0.005)[0]
+    factors = {}
+    for interp in ("constant", "linear"):
+        lev = hierarchy(K, n, n, 64, interp=interp)
+        mm = [_m_matrix(S + tau * Kl) for (_, _, S, Kl, _, _) in lev]
+        D = (lev[0][2] + tau * lev[0][3]).tocsr()
+        e = np.random.default_rng(0).standard_normal(n * n)
+        for _ in range(8):
+            e2 = e - vcycle(lev, tau, D @ e)
+            f = np.linalg.norm(e2) / np.linalg.norm(e)
+            e = e2 / np.linalg.norm(e2)
+        factors[interp] = (all(mm), f)
+    assert factors["constant"][0] and factors["constant"][1] < 0.75
+    assert not factors["linear"][0] and factors["linear"][1] > 1.0
