@@ -325,7 +325,9 @@ __global__ void __launch_bounds__(64 * kWaves)
   wrestrict<T, NPT, MODE, R, HX, HY>(o, x, b, X0, Y0, rc);
 }
 
-template <typename T, int NPT, int MODE, int R, int NU, int H>
+// LIN: linear interpolation (weights 3/4 and 1/4 built in, pw at the
+// boundary); otherwise the weights pa, pn, pw of the operator.
+template <typename T, int NPT, int MODE, int R, int NU, int H, bool LIN>
 __device__ __forceinline__ void wup_body(const WOp<T> &o, T (&x)[R], const T (&b)[R], int X0,
                                          int Y0, const T *se, int CW, int CX0, int CY0) {
   wpresmooth<T, NPT, MODE, R, NU>(o, x, b, X0, Y0);
@@ -337,7 +339,8 @@ __device__ __forceinline__ void wup_body(const WOp<T> &o, T (&x)[R], const T (&b
   const int Ix = gx >> 1;
   const int nbx = (gx & 1) ? Ix + 1 : Ix - 1;
   const bool ix = nbx >= 0 && nbx < ncx;
-  const bool hx = ix && o.pn != T(0);
+  const T pa = LIN ? T(0.75) : o.pa, pn = LIN ? T(0.25) : o.pn;
+  const bool hx = ix && (LIN || pn != T(0));
   const bool in_x = gx >= 0 && gx < o.nx && lane >= M && lane < 64 - M;
 #pragma unroll
   for (int r = M; r < R - M; ++r) {
@@ -345,22 +348,22 @@ __device__ __forceinline__ void wup_body(const WOp<T> &o, T (&x)[R], const T (&b
     const int Iy = gy >> 1;
     const int nby = (gy & 1) ? Iy + 1 : Iy - 1;
     const bool iy = nby >= 0 && nby < ncy;
-    const bool hy = iy && o.pn != T(0);
+    const bool hy = iy && (LIN || pn != T(0));
     if (in_x && gy >= 0 && gy < o.ny) {
       const T *row = se + (Iy - CY0) * CW;
       const T *nrow = se + (nby - CY0) * CW;
-      const T wx = ix ? o.pa : o.pw, wy = iy ? o.pa : o.pw;
+      const T wx = ix ? pa : o.pw, wy = iy ? pa : o.pw;
       T pv = wx * wy * row[Ix - CX0];
-      if (hx) pv += o.pn * wy * row[nbx - CX0];
-      if (hy) pv += wx * o.pn * nrow[Ix - CX0];
-      if (hx && hy) pv += o.pn * o.pn * nrow[nbx - CX0];
+      if (hx) pv += pn * wy * row[nbx - CX0];
+      if (hy) pv += wx * pn * nrow[Ix - CX0];
+      if (hx && hy) pv += (LIN ? T(0.0625) : pn * pn) * nrow[nbx - CX0];
       x[r] += pv;
     }
   }
   wpostsmooth<T, NPT, MODE, R, NU>(o, x, b, X0, Y0);
 }
 
-template <typename T, int NPT, int NU, int MODE>
+template <typename T, int NPT, int NU, int MODE, bool LIN>
 __global__ void __launch_bounds__(64 * kWaves)
     k_wup(OpView<T> D, const T *__restrict__ bin, const T *__restrict__ ec, T *__restrict__ xout) {
   constexpr int H = WGeom<T, NU>::HU;
@@ -386,7 +389,7 @@ __global__ void __launch_bounds__(64 * kWaves)
   __syncthreads();
   if (OY >= D.ny) return;
   WOp<T> o = make_wop(D);
-  wup_body<T, NPT, MODE, R, NU, H>(o, x, b, X0, Y0, se, CW, CX0, CY0);
+  wup_body<T, NPT, MODE, R, NU, H, LIN>(o, x, b, X0, Y0, se, CW, CX0, CY0);
   const int gx = X0 + lane;
   if (lane >= H && lane < 64 - H && gx < D.nx) {
 #pragma unroll
@@ -416,7 +419,10 @@ void launch_wup(const OpView<T> &D, const T *b, const T *ec, T *x, hipStream_t s
   constexpr int TY = WGeom<T, NU>::TYU;
   constexpr int TXO = 64 - 2 * H;
   dim3 grid((D.nx + TXO - 1) / TXO, (D.ny + TY * kWaves - 1) / (TY * kWaves));
-  k_wup<T, NPT, NU, MODE><<<grid, 64 * kWaves, 0, st>>>(D, b, ec, x);
+  if (D.pa == T(0.75) && D.pn == T(0.25))
+    k_wup<T, NPT, NU, MODE, true><<<grid, 64 * kWaves, 0, st>>>(D, b, ec, x);
+  else
+    k_wup<T, NPT, NU, MODE, false><<<grid, 64 * kWaves, 0, st>>>(D, b, ec, x);
 }
 
 }  // namespace
