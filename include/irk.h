@@ -120,6 +120,12 @@ typedef struct {
                       the transpose of the restriction, which keeps every
                       Galerkin coarse operator of an M-matrix an M-matrix
                       (advection-dominated operators at large h_t). */
+  int graphs;      /* 1: each preconditioner application (s coupling passes
+                      and V-cycles, a fixed kernel sequence per Krylov column)
+                      is captured once into a HIP graph and replayed, which
+                      lowers the per-kernel launch cost; 0: direct launches.
+                      Both run the same kernels in the same order, so the
+                      results are identical. */
 } irk_options;
 
 typedef struct {
@@ -132,7 +138,8 @@ typedef struct {
 
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
- * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR. */
+ * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR,
+ * graphs 1. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.
@@ -220,6 +227,13 @@ const char *irk_last_error(const irk_solver *S);
  * level operators were recognised as constant-coefficient (1) or are stored
  * per node (0).  Any pointer may be NULL. */
 irk_status irk_info(const irk_solver *S, int *N, int *s, int *levels, int *constant_coeff);
+
+/* Preconditioner graphs (option graphs = 1): the number of captured graphs
+ * the solver holds (one per Krylov column and system kind used so far) and
+ * the number of replays since setup.  A class selected with
+ * irk_profile_select that runs inside the preconditioner switches the
+ * replays off while it is selected.  Any pointer may be NULL. */
+irk_status irk_graph_stats(const irk_solver *S, int *graphs, long long *replays);
 
 /* Kernel classes for irk_profile_select. */
 enum {

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
                 ("coarse_max", ctypes.c_int), ("vcycles", ctypes.c_int),
                 ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("side", ctypes.c_int),
-                ("interp", ctypes.c_int)]
+                ("interp", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -92,6 +92,8 @@ _PROTOS = {
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "irk_info": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "irk_graph_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_longlong)]),
 }
 
 

@@ -129,6 +129,16 @@ struct irk_solver {
   long long prof_launches = 0;
   double prof_ms = 0.0, prof_bytes = 0.0;
 
+  // preconditioner applications captured as HIP graphs, one per argument set
+  // (Krylov column j of a system); dropped when the operators change
+  struct PrecGraph {
+    const void *v, *scale, *z, *C, *ord;
+    hipGraphExec_t exec;
+  };
+  std::vector<PrecGraph> graphs;
+  hipStream_t cap_stream = nullptr;  // capture only; replays go to `stream`
+  long long graph_replays = 0;
+
   std::string err;
 };
 
@@ -243,7 +253,17 @@ irk::Interp interp_of(const irk_solver *S, int l) {
 // Build the operators: K (and M) on the fine grid and, for every stage block
 // D_i = M + tau_i K (Sec. 4.2), the Galerkin hierarchy S_l + tau_i K_l and the
 // dense inverse on the coarsest level.
+// Destroy the captured preconditioner graphs (their kernel arguments point at
+// the operators being replaced).
+void drop_graphs(irk_solver *S) {
+  if (S->graphs.empty()) return;
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  for (const auto &g : S->graphs) (void)hipGraphExecDestroy(g.exec);
+  S->graphs.clear();
+}
+
 irk_status build_operators(irk_solver *S, const irk_csr *K) {
+  drop_graphs(S);
   Stencil9 K0;
   if (!irk::csr_to_stencil(K->n, K->rowptr, K->colind, K->val, S->nx, S->ny, K0, S->err))
     return IRK_E_INVALID;
@@ -628,6 +648,64 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
   }
 }
 
+// Kernel classes launched inside apply_precond: timing one of them needs the
+// direct launches (events between kernels).
+bool prof_in_precond(const irk_solver *S) {
+  switch (S->prof_sel) {
+    case IRK_KC_COUPLE:
+    case IRK_KC_VDOWN_L0:
+    case IRK_KC_VMID_DOWN:
+    case IRK_KC_VTAIL:
+    case IRK_KC_VMID_UP:
+    case IRK_KC_VUP_L0:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// apply_precond through a HIP graph: the kernel sequence of one argument set
+// is captured on a private stream the first time (capture records, it does
+// not run) and replayed on the solver's stream after that.  The sequence
+// holds kernel launches only (no memory set or copy nodes).
+template <typename T>
+void precondition(irk_solver *S, const double *v, const double *scale_j, T *z, const double *C,
+                  const int *ord) {
+  if (!S->opt.graphs || prof_in_precond(S)) return apply_precond<T>(S, v, scale_j, z, C, ord);
+  const irk_solver::PrecGraph *hit = nullptr;
+  for (const auto &g : S->graphs)
+    if (g.v == v && g.scale == scale_j && g.z == z && g.C == C && g.ord == ord) {
+      hit = &g;
+      break;
+    }
+  if (!hit) {
+    if (S->graphs.size() >= 256) drop_graphs(S);
+    if (!S->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
+    const hipStream_t run = S->stream;
+    HIP_TRY(hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal));
+    S->stream = S->cap_stream;
+    hipGraph_t g = nullptr;
+    try {
+      apply_precond<T>(S, v, scale_j, z, C, ord);
+    } catch (...) {
+      S->stream = run;
+      (void)hipStreamEndCapture(S->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    S->stream = run;
+    HIP_TRY(hipStreamEndCapture(S->cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw HipError{e, "hipGraphInstantiate"};
+    S->graphs.push_back({v, scale_j, z, C, ord, ex});
+    hit = &S->graphs.back();
+  }
+  HIP_TRY(hipGraphLaunch(hit->exec, S->stream));
+  ++S->graph_replays;
+}
+
 struct SystemDesc {
   const double *hA;  // s x s matrix of the SpMM (h A or h A^T)
   const double *C;   // coupling h A~ without diagonal (row i = stage i)
@@ -686,7 +764,7 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     for (; j < m; ++j) {
       const double *Vj = S->V + (size_t)j * sN;
       T *Zj = Z + (size_t)j * sN;
-      apply_precond<T>(S, Vj, S->scale + j, Zj, sys.C, sys.ord);
+      precondition<T>(S, Vj, S->scale + j, Zj, sys.C, sys.ord);
       const double kb = op_bytes(S, N, S->K64.npt, 8);
       const double zb = (double)sN * sizeof(T), vb = (double)sN * 8.0;
       ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb);
@@ -803,7 +881,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
   HIP_TRY(hipMemsetAsync(S->acc, 0, sN * sizeof(double), st));
   rhs_forward(K, sys.u, S->g, s, S->f, S->V, S->partial, st);
   // V_0 = P^-1 (1 (x) f), lazily normalised
-  apply_precond<double>(S, S->V, S->one, Z, sys.C, sys.ord);
+  precondition<double>(S, S->V, S->one, Z, sys.C, sys.ord);
   rhs_copy(Z, sN, S->V, S->partial, st);
   finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
   HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -835,7 +913,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       double *Zj = Z + (size_t)j * sN;
       double *Vn = S->V + (size_t)(j + 1) * sN;
       kron_apply(K, mass(S), Vj, sys.hA, s, u, st);
-      apply_precond<double>(S, u, S->scale + j, Zj, sys.C, sys.ord);
+      precondition<double>(S, u, S->scale + j, Zj, sys.C, sys.ord);
       rhs_copy(Zj, sN, Vn, S->partial, st);
       // two classical Gram-Schmidt passes (h1, then h2)
       vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
@@ -882,7 +960,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     if (status == IRK_OK && !S->opt.true_resid) break;
     // preconditioned residual of the accumulated solution: P^-1 (rhs - A k)
     residual_full(K, mass(S), S->acc, sys.hA, s, nullptr, S->f, S->V, S->partial, st);
-    apply_precond<double>(S, S->V, S->one, Z, sys.C, sys.ord);
+    precondition<double>(S, S->V, S->one, Z, sys.C, sys.ord);
     rhs_copy(Z, sN, S->V, S->partial, st);
     finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
     HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -939,6 +1017,7 @@ bool valid_options(const irk_options &o, std::string &err) {
   if (o.side != IRK_RIGHT && o.side != IRK_LEFT) return err = "side must be IRK_RIGHT or IRK_LEFT", false;
   if (o.interp != IRK_INTERP_LINEAR && o.interp != IRK_INTERP_CONSTANT)
     return err = "interp must be IRK_INTERP_LINEAR or IRK_INTERP_CONSTANT", false;
+  if (o.graphs != 0 && o.graphs != 1) return err = "graphs must be 0 or 1", false;
   if (o.side == IRK_LEFT && o.precision != IRK_FP64)
     return err = "left preconditioning needs precision IRK_FP64", false;
   return true;
@@ -983,6 +1062,7 @@ void irk_default_options(irk_options *o) {
   o->rtol = 1e-8;
   o->side = IRK_RIGHT;
   o->interp = IRK_INTERP_LINEAR;
+  o->graphs = 1;
 }
 
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {
@@ -1232,11 +1312,11 @@ irk_status irk_apply_preconditioner(irk_solver *S, const double *v_dev, double *
     HIP_TRY(hipMemcpyAsync(S->y, &one, sizeof(double), hipMemcpyHostToDevice, S->stream));
     HIP_TRY(hipMemsetAsync(z_dev, 0, S->sN * sizeof(double), S->stream));
     if (S->opt.precision == IRK_MIXED) {
-      apply_precond<float>(S, S->V, S->scale, static_cast<float *>(S->Z), S->Cfwd, S->ord_fwd);
+      precondition<float>(S, S->V, S->scale, static_cast<float *>(S->Z), S->Cfwd, S->ord_fwd);
       irk::kern::accumulate_solution<float>(static_cast<float *>(S->Z), S->sN, S->y, 1, S->sN,
                                             z_dev, S->stream);
     } else {
-      apply_precond<double>(S, S->V, S->scale, static_cast<double *>(S->Z), S->Cfwd, S->ord_fwd);
+      precondition<double>(S, S->V, S->scale, static_cast<double *>(S->Z), S->Cfwd, S->ord_fwd);
       irk::kern::accumulate_solution<double>(static_cast<double *>(S->Z), S->sN, S->y, 1, S->sN,
                                              z_dev, S->stream);
     }
@@ -1253,6 +1333,8 @@ void irk_destroy(irk_solver *S) {
     (void)hipEventDestroy(t.b);
   }
   for (hipEvent_t e : S->prof_pool) (void)hipEventDestroy(e);
+  for (const auto &g : S->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
   free_list(S->op_allocs);
   free_list(S->ws_allocs);
   if (S->host_resid) (void)hipHostFree(S->host_resid);
@@ -1296,6 +1378,13 @@ irk_status irk_profile_read(const irk_solver *S, long long *launches, double *to
   if (launches) *launches = S->prof_launches;
   if (total_ms) *total_ms = S->prof_ms;
   if (total_bytes) *total_bytes = S->prof_bytes;
+  return IRK_OK;
+}
+
+irk_status irk_graph_stats(const irk_solver *S, int *graphs, long long *replays) {
+  if (!S) return IRK_E_INVALID;
+  if (graphs) *graphs = (int)S->graphs.size();
+  if (replays) *replays = S->graph_replays;
   return IRK_OK;
 }
 

@@ -96,15 +96,31 @@ __device__ __forceinline__ Co side_coefs(const S9Op &o, bool edge) {
   return r;
 }
 
-// Lane coefficients of the middle rows (selected once per wave).
-struct MidCo {
+// Lane coefficients of a boundary tile, selected once per wave: the grid's
+// first row (tile row H when the tile holds it), its last row (tile row
+// H + TY - 1) and every other row.  Selecting them up front keeps the class
+// table out of the registers for the rest of the kernel.
+struct RowCo {
   Co a, b;
+};
+struct MidCo {
+  RowCo top, mid, bot;
 };
 
 __device__ __forceinline__ MidCo mid_coefs(const S9Op &o, const Place &p) {
   MidCo m;
-  m.a = side_coefs<1, 0>(o, p.fcol);
-  m.b = side_coefs<1, 2>(o, p.lcol);
+  m.mid.a = side_coefs<1, 0>(o, p.fcol);
+  m.mid.b = side_coefs<1, 2>(o, p.lcol);
+  m.top = m.mid;
+  m.bot = m.mid;
+  if (p.top) {
+    m.top.a = side_coefs<0, 0>(o, p.fcol);
+    m.top.b = side_coefs<0, 2>(o, p.lcol);
+  }
+  if (p.bot) {
+    m.bot.a = side_coefs<2, 0>(o, p.fcol);
+    m.bot.b = side_coefs<2, 2>(o, p.lcol);
+  }
   return m;
 }
 
@@ -128,17 +144,14 @@ struct Ctx {
   const S9Op &o;
   const Place &p;
   const MidCo &m;
+  // r is a compile-time row index after unrolling, so these fold to one set
   __device__ __forceinline__ Co a(int r) const {
     if (!BOUND) return side_coefs<1, 1>(o, false);
-    if (r == H && p.top) return side_coefs<0, 0>(o, p.fcol);
-    if (r == H + TY - 1 && p.bot) return side_coefs<2, 0>(o, p.fcol);
-    return m.a;
+    return r == H ? m.top.a : (r == H + TY - 1 ? m.bot.a : m.mid.a);
   }
   __device__ __forceinline__ Co b(int r) const {
     if (!BOUND) return side_coefs<1, 1>(o, false);
-    if (r == H && p.top) return side_coefs<0, 2>(o, p.lcol);
-    if (r == H + TY - 1 && p.bot) return side_coefs<2, 2>(o, p.lcol);
-    return m.b;
+    return r == H ? m.top.b : (r == H + TY - 1 ? m.bot.b : m.mid.b);
   }
 };
 

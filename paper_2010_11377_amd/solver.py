@@ -44,7 +44,8 @@ class IRKSolver:
 
     def __init__(self, A, b, c, K, h_t, grid, precision="fp64", precond="LD", restart=40,
                  max_iter=200, nu_pre=2, nu_post=2, coarse_max=64, rtol=1e-8, true_resid=True,
-                 reorth=0, side="right", M=None, interp="linear", device=None):
+                 reorth=0, side="right", M=None, interp="linear", graphs=True,
+                 device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("IRKSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = B.lib()
@@ -69,6 +70,7 @@ class IRKSolver:
         opt.reorth = int(reorth)
         opt.side = {"right": B.IRK_RIGHT, "left": B.IRK_LEFT}[side]
         opt.interp = {"linear": B.IRK_INTERP_LINEAR, "constant": B.IRK_INTERP_CONSTANT}[interp]
+        opt.graphs = 1 if graphs else 0
         self.options = opt
         tab = B.Butcher(self.s, B.dptr(self.A), B.dptr(self._b), B.dptr(self._c))
         csr, keep = _csr_struct(*K)
@@ -113,6 +115,12 @@ class IRKSolver:
         self._check(self.lib.irk_info(self._h, ctypes.byref(N), ctypes.byref(s), ctypes.byref(lev),
                                       ctypes.byref(cc)))
         return {"N": N.value, "s": s.value, "levels": lev.value, "constant_coeff": bool(cc.value)}
+
+    def graph_stats(self):
+        """(captured preconditioner graphs, replays since setup)."""
+        g, r = ctypes.c_int(), ctypes.c_longlong()
+        self._check(self.lib.irk_graph_stats(self._h, ctypes.byref(g), ctypes.byref(r)))
+        return g.value, r.value
 
     # -- problem data ----------------------------------------------------------
     def set_source(self, g):

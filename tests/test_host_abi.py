@@ -43,6 +43,8 @@ def test_default_options():
             o.vcycles, o.true_resid, o.reorth) == (0, 0, 40, 200, 2, 2, 64, 1, 1, 0)
     assert o.rtol == 1e-8
     assert o.side == B.IRK_RIGHT
+    assert o.interp == B.IRK_INTERP_LINEAR
+    assert o.graphs == 1
 
 
 def test_status_strings():
@@ -108,6 +110,10 @@ def test_setup_validation_before_any_device_work():
     opt.side = 2
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
     assert st == B.IRK_E_INVALID and "side" in msg
+    opt = B.default_options()
+    opt.graphs = 2
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
+    assert st == B.IRK_E_INVALID and "graphs" in msg
     opt = B.default_options()
     opt.side, opt.precision = B.IRK_LEFT, B.IRK_MIXED
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
