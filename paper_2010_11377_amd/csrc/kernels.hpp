@@ -111,14 +111,10 @@ void wup(const OpView<T> &D, int nu, const T *b, const T *ec, T *x, hipStream_t 
 // FP32 finest-level passes with two adjacent columns per lane (wsplit.hip):
 // every lane updates one node per row in each colour half sweep.  Uniform
 // five-point operators on grids with even nx and ny; `interior` is a host
-// copy of the interior-class coefficients (9 entries) of D, resp. K.
+// copy of the interior-class coefficients (9 entries) of D.
 bool wsplit_ok(const OpView<float> &D);
 void sdown(const OpView<float> &D, const float *interior, int nu, const float *b, float *rc,
            hipStream_t st);
-void sdown_couple(const OpView<float> &D, const float *interior, const OpView<float> &K,
-                  const float *k_interior, int nu, const double *v, const double *scale_j,
-                  const float *z, const double *C, int s, int i, float *b_out, float *rc,
-                  hipStream_t st);
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st);
 // FP32 nine-point constant-coefficient levels, two columns per lane

@@ -35,10 +35,6 @@ __device__ __forceinline__ float s_prev(float v) {  // value of lane - 1 (0 in l
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
-struct Row8s {
-  double c[8];
-};
-
 // Interior five-point coefficients: south (k=1), west (3), centre (4),
 // east (5), north (7), and 1 / centre.
 struct SOp {
@@ -65,6 +61,170 @@ template <int R>
 struct STile {
   float xa[R], xb[R], ba[R], bb[R];
 };
+
+// Row pipeline of the down pass.  The pass is a sequence of stages (the
+// first colour-0 half sweep from x = 0, the red-black half sweeps, the
+// restriction), each over a range of tile rows.  Stage k touches row r at
+// step r + kSkew k.  Every stage reads rows r - 1 .. r + 1 as the previous
+// stage left them (a five-point half sweep reads the other colour, which
+// only the previous half sweep wrote): with kSkew = 2, at step r + 2k row
+// r + 1 has been through stage k - 1 (step r + 2k - 1) but not k, and row
+// r - 1 through stage k but not k + 1 (step r + 2k + 1), which are exactly
+// the values a stage-by-stage order reads; the stages of one step are
+// independent of each other, so the wave has several row updates in flight.
+// Row by row, it works on the first rows while the later ones are still
+// loading, and writes its outputs while it is still computing.  The down
+// pass is latency bound (a few hundred instructions per wave after long
+// loads), so this overlap is what counts; the up pass, bound by its
+// arithmetic, keeps the stage-by-stage order below.
+constexpr int kSkew = 2;
+
+// Stage 0: x = b / d on colour 0 (slot a of even rows, slot b of odd rows)
+// and zero on colour 1; b is zero outside the grid, so this x is too.
+template <int R>
+__device__ __forceinline__ void s_init_row(const SOp &o, STile<R> &t, int r) {
+  if ((r & 1) == 0) {
+    t.xa[r] = t.ba[r] * o.inv;
+    t.xb[r] = 0.0f;
+  } else {
+    t.xb[r] = t.bb[r] * o.inv;
+    t.xa[r] = 0.0f;
+  }
+}
+
+// One row of a colour half sweep with 1 / centre = inv: the lanes outside
+// the grid take inv = 0, which keeps them at zero (rows outside the grid are
+// skipped altogether).
+template <int R>
+__device__ __forceinline__ void s_relax_row(const SOp &o, STile<R> &t, int r, int color,
+                                            float inv) {
+  if ((r & 1) == color) {  // slot a has colour r mod 2
+    t.xa[r] = (t.ba[r] - o.s * t.xa[r - 1] - o.n * t.xa[r + 1] - o.w * s_prev(t.xb[r]) -
+               o.e * t.xb[r]) * inv;
+  } else {
+    t.xb[r] = (t.bb[r] - o.s * t.xb[r - 1] - o.n * t.xb[r + 1] - o.w * t.xa[r] -
+               o.e * s_next(t.xa[r])) * inv;
+  }
+}
+
+// Residual b - D x of row r, summed over the lane's two slots.
+template <int R>
+__device__ __forceinline__ float s_resid_pair(const SOp &o, const STile<R> &t, int r) {
+  const float ra = t.ba[r] - o.c * t.xa[r] - o.s * t.xa[r - 1] - o.n * t.xa[r + 1] -
+                   o.w * s_prev(t.xb[r]) - o.e * t.xb[r];
+  const float rb = t.bb[r] - o.c * t.xb[r] - o.s * t.xb[r - 1] - o.n * t.xb[r + 1] -
+                   o.w * t.xa[r] - o.e * s_next(t.xa[r]);
+  return ra + rb;
+}
+
+// Rows Y0..Y0+R-1 of a grid vector, columns X0+2l and X0+2l+1, zero outside.
+template <int R>
+__device__ __forceinline__ void s_load(const float *__restrict__ g, float (&a)[R], float (&b)[R],
+                                       int X0, int Y0, int nx, int ny) {
+  const int gx = X0 + 2 * s_lane();
+  const bool inx = gx >= 0 && gx < nx;  // nx and gx even: gx + 1 < nx too
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = Y0 + r;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const float2 *>(g + (size_t)gy * nx + gx);
+    a[r] = v.x;
+    b[r] = v.y;
+  }
+}
+
+__device__ __forceinline__ bool s_interior(int X0, int Y0, int R, int nx, int ny) {
+  return X0 >= 0 && Y0 >= 0 && X0 + 128 <= nx && Y0 + R <= ny;
+}
+
+__host__ __device__ constexpr int even_up(int h) { return (h + 1) & ~1; }
+
+// Tile geometry: TY output rows per wave, R = TY + 2H register rows, TXO
+// output columns.  The down pass needs x exact on margin 2 nu + 1 for its
+// residual; the up pass repeats the 2 nu pre-sweeps and adds 2 nu
+// post-sweeps.  Halos are even so that the tile origin stays even.  Short
+// down tiles: the latency-bound down pass runs best with many short waves
+// (two or three per SIMD hide each other's load latency); the up pass is
+// bound by its arithmetic, where the halo's share of the work decides.
+template <int NU>
+struct SGeomD {
+  static constexpr int H = even_up(2 * NU);
+  static constexpr int TY = 16;
+  static constexpr int R = TY + 2 * H;
+  static constexpr int TXO = 128 - 2 * H;
+};
+template <int NU>
+struct SGeomU {
+  static constexpr int H = even_up(4 * NU - 1);
+  static constexpr int TY = NU == 1 ? 32 : (NU == 2 ? 24 : 16);
+  static constexpr int R = TY + 2 * H;
+  static constexpr int TXO = 128 - 2 * H;
+};
+
+// Pre-smoothing from x = 0 (stage 0, then 2 nu - 1 half sweeps; sweep k
+// covers rows [k, R - k) in colour k mod 2) and rc = R (b - D x) with R the
+// sum over 2 x 2 cells: coarse node (I, J) takes fine columns 2I, 2I+1 of
+// rows 2J, 2J+1, i.e. both slots of one lane in two rows.  Written for output
+// rows [H, R-H) and lanes [H/2, 64-H/2); the pair of rows r0, r0 + 1 is
+// restricted once rows r0 - 1 .. r0 + 2 are final.
+//
+// BOUND: the tile reaches past the grid.  Its nodes outside stay zero: rows
+// outside (Y0 is the same for the whole wave, so the test is a scalar
+// branch) are never updated, lanes outside relax with inv = 0, and the
+// residual of an outside node (nonzero next to a nonzero inside one) is left
+// out of the sums.
+template <bool BOUND, int R, int NU, int H>
+__device__ __forceinline__ void s_down_rows(const SOp &o, STile<R> &t, int X0, int Y0,
+                                            float *__restrict__ rc) {
+  constexpr int K = 2 * NU;
+  const int lane = s_lane();
+  const int gxa = X0 + 2 * lane;
+  const int ncx = o.nx / 2, ncy = o.ny / 2;
+  const int I = gxa >> 1;
+  const bool inx = gxa >= 0 && gxa < o.nx;  // nx even: slot b is inside iff slot a is
+  const bool lane_out = lane >= H / 2 && lane < 64 - H / 2 && I < ncx;
+  const float inv = BOUND && !inx ? 0.0f : o.inv;
+  auto row_in = [&](int r) { return !BOUND || (unsigned)(Y0 + r) < (unsigned)o.ny; };
+#pragma unroll
+  for (int step = 0; step < R + kSkew * K; ++step) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int r = step - kSkew * k;
+      if (k == 0 && r < R) {
+        s_init_row<R>(o, t, r);
+      } else if (k > 0 && r >= k && r < R - k) {
+        if (row_in(r)) s_relax_row<R>(o, t, r, k & 1, inv);
+      }
+    }
+    // the pair r0, r0 + 1 once stage K - 1 has passed row r0 + 2
+    const int r0 = step - 2 - kSkew * (K - 1);
+    if (r0 >= H && r0 < R - H && ((r0 - H) & 1) == 0) {
+      float sum = 0.0f;
+      if (row_in(r0)) sum += s_resid_pair<R>(o, t, r0);
+      if (row_in(r0 + 1)) sum += s_resid_pair<R>(o, t, r0 + 1);
+      if (BOUND && !inx) sum = 0.0f;
+      const int J = (Y0 + r0) >> 1;
+      if (lane_out && J < ncy) rc[(size_t)J * ncx + I] = sum;
+    }
+  }
+}
+
+template <int NU>
+__global__ void __launch_bounds__(64 * kSW)
+    k_sdown(SOp o, const float *__restrict__ bin, float *__restrict__ rc) {
+  using G = SGeomD<NU>;
+  constexpr int H = G::H, TY = G::TY, R = G::R;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // Y0 uniform
+  const int OX = blockIdx.x * G::TXO, OY = (blockIdx.y * kSW + wave) * TY;
+  if (OY >= o.ny) return;
+  const int X0 = OX - H, Y0 = OY - H;
+  STile<R> t;
+  s_load<R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  if (s_interior(X0, Y0, R, o.nx, o.ny))
+    s_down_rows<false, R, NU, H>(o, t, X0, Y0, rc);
+  else
+    s_down_rows<true, R, NU, H>(o, t, X0, Y0, rc);
+}
 
 // One colour half sweep over rows [M, R-M).  BOUND: the tile reaches past the
 // grid, whose outside nodes are kept at zero.
@@ -129,159 +289,6 @@ __device__ __forceinline__ void s_post(const SOp &o, STile<R> &t, int X0, int Y0
   if (NU >= 3) {
     s_sweep<BOUND, R, M0 + 4>(o, t, X0, Y0, 1);
     s_sweep<BOUND, R, M0 + 5>(o, t, X0, Y0, 0);
-  }
-}
-
-// rc = R (b - D x) with R the sum over 2 x 2 cells: coarse node (I, J) takes
-// fine columns 2I, 2I+1 of rows 2J, 2J+1, i.e. both slots of one lane in two
-// rows.  Written for output rows [H, R-H) and lanes [H/2, 64-H/2).
-template <bool BOUND, int R, int H>
-__device__ __forceinline__ void s_restrict(const SOp &o, const STile<R> &t, int X0, int Y0,
-                                           float *__restrict__ rc) {
-  const int lane = s_lane();
-  const int gxa = X0 + 2 * lane;
-  const int ncx = o.nx / 2, ncy = o.ny / 2;
-  const int I = gxa >> 1;
-  const bool inx = gxa >= 0 && gxa < o.nx;
-  const bool lane_out = lane >= H / 2 && lane < 64 - H / 2 && I < ncx;
-#pragma unroll
-  for (int r = H; r < R - H; r += 2) {
-    float sum = 0.0f;
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int rr = r + d;
-      const float ra = t.ba[rr] - o.c * t.xa[rr] - o.s * t.xa[rr - 1] - o.n * t.xa[rr + 1] -
-                       o.w * s_prev(t.xb[rr]) - o.e * t.xb[rr];
-      const float rb = t.bb[rr] - o.c * t.xb[rr] - o.s * t.xb[rr - 1] - o.n * t.xb[rr + 1] -
-                       o.w * t.xa[rr] - o.e * s_next(t.xa[rr]);
-      // a zero node outside the grid next to a nonzero one has a nonzero
-      // residual: mask it
-      const int gy = Y0 + rr;
-      const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
-      sum += in ? ra + rb : 0.0f;
-    }
-    const int J = (Y0 + r) >> 1;
-    if (lane_out && J < ncy) rc[(size_t)J * ncx + I] = sum;
-  }
-}
-
-// Rows Y0..Y0+R-1 of a grid vector, columns X0+2l and X0+2l+1, zero outside.
-template <int R>
-__device__ __forceinline__ void s_load(const float *__restrict__ g, float (&a)[R], float (&b)[R],
-                                       int X0, int Y0, int nx, int ny) {
-  const int gx = X0 + 2 * s_lane();
-  const bool inx = gx >= 0 && gx < nx;  // nx and gx even: gx + 1 < nx too
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int gy = Y0 + r;
-    float2 v = make_float2(0.0f, 0.0f);
-    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const float2 *>(g + (size_t)gy * nx + gx);
-    a[r] = v.x;
-    b[r] = v.y;
-  }
-}
-
-__device__ __forceinline__ bool s_interior(int X0, int Y0, int R, int nx, int ny) {
-  return X0 >= 0 && Y0 >= 0 && X0 + 128 <= nx && Y0 + R <= ny;
-}
-
-__host__ __device__ constexpr int even_up(int h) { return (h + 1) & ~1; }
-
-// Output rows per wave (TY) and register rows (R = TY + 2H).  The down pass
-// needs x exact on margin 2 nu + 1 for its residual (one more with the
-// coupling, whose right-hand side is exact only on margin 1 in x); the up
-// pass repeats the 2 nu pre-sweeps and adds 2 nu post-sweeps.  Halos are
-// even so that the tile origin stays even.
-template <int NU, bool COUPLE>
-struct SGeomD {
-  static constexpr int H = even_up(2 * NU + (COUPLE ? 1 : 0));
-  static constexpr int TY = 32;
-  static constexpr int R = TY + 2 * H;
-  static constexpr int TXO = 128 - 2 * H;
-};
-template <int NU>
-struct SGeomU {
-  static constexpr int H = even_up(4 * NU - 1);
-  static constexpr int TY = NU == 1 ? 32 : (NU == 2 ? 24 : 16);
-  static constexpr int R = TY + 2 * H;
-  static constexpr int TXO = 128 - 2 * H;
-};
-
-template <int NU, bool COUPLE>
-__global__ void __launch_bounds__(64 * kSW)
-    k_sdown(SOp o, SOp ko, const double *__restrict__ v, const double *__restrict__ scale_j,
-            const float *__restrict__ z, Row8s crow, int s, int i, const float *__restrict__ bin,
-            float *__restrict__ b_out, float *__restrict__ rc) {
-  using G = SGeomD<NU, COUPLE>;
-  constexpr int H = G::H, TY = G::TY, R = G::R;
-  const int wave = threadIdx.x >> 6, lane = s_lane();
-  const int OX = blockIdx.x * G::TXO, OY = (blockIdx.y * kSW + wave) * TY;
-  if (OY >= o.ny) return;
-  const int X0 = OX - H, Y0 = OY - H;
-  const int gxa = X0 + 2 * lane;
-  STile<R> t;
-  if (COUPLE) {
-    // b = scale_j v_i - K c with c = sum_k C[k] z_k, c on rows Y0-1 .. Y0+R
-    const size_t N = (size_t)o.nx * o.ny;
-    const double sc = *scale_j;
-    const bool inx = gxa >= 0 && gxa < o.nx;
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < kMaxStages; ++k)
-      if (k < s && crow.c[k] != 0.0) any = true;
-    float ca[R + 2], cb[R + 2];
-#pragma unroll
-    for (int r = 0; r < R + 2; ++r) {
-      const int gy = Y0 - 1 + r;
-      float2 acc = make_float2(0.0f, 0.0f);
-      if (any && inx && gy >= 0 && gy < o.ny) {
-        const size_t p = (size_t)gy * o.nx + gxa;
-#pragma unroll
-        for (int k = 0; k < kMaxStages; ++k)
-          if (k < s && crow.c[k] != 0.0) {
-            const float2 zz = *reinterpret_cast<const float2 *>(z + (size_t)k * N + p);
-            const float ck = (float)crow.c[k];
-            acc.x += ck * zz.x;
-            acc.y += ck * zz.y;
-          }
-      }
-      ca[r] = acc.x;
-      cb[r] = acc.y;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int gy = Y0 + r;
-      const bool in = inx && gy >= 0 && gy < o.ny;
-      double2 vv = make_double2(0.0, 0.0);
-      if (in) vv = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * o.nx + gxa);
-      float va = (float)(sc * vv.x), vb = (float)(sc * vv.y);
-      if (any && in) {
-        va -= ko.c * ca[r + 1] + ko.s * ca[r] + ko.n * ca[r + 2] + ko.w * s_prev(cb[r + 1]) +
-              ko.e * cb[r + 1];
-        vb -= ko.c * cb[r + 1] + ko.s * cb[r] + ko.n * cb[r + 2] + ko.w * ca[r + 1] +
-              ko.e * s_next(ca[r + 1]);
-      }
-      t.ba[r] = va;
-      t.bb[r] = vb;
-    }
-    // the right-hand side of the output region, for the up pass
-    if (lane >= H / 2 && lane < 64 - H / 2 && gxa < o.nx) {
-#pragma unroll
-      for (int r = H; r < R - H; ++r) {
-        const int gy = Y0 + r;
-        if (gy < o.ny)
-          *reinterpret_cast<float2 *>(b_out + (size_t)gy * o.nx + gxa) = make_float2(t.ba[r], t.bb[r]);
-      }
-    }
-  } else {
-    s_load<R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
-  }
-  if (s_interior(X0, Y0, R, o.nx, o.ny)) {
-    s_pre<false, R, NU>(o, t, X0, Y0);
-    s_restrict<false, R, H>(o, t, X0, Y0, rc);
-  } else {
-    s_pre<true, R, NU>(o, t, X0, Y0);
-    s_restrict<true, R, H>(o, t, X0, Y0, rc);
   }
 }
 
@@ -441,33 +448,18 @@ __global__ void __launch_bounds__(64 * kSW)
   }
 }
 
-template <int NU, bool COUPLE>
-dim3 sdown_grid(int nx, int ny) {
-  using G = SGeomD<NU, COUPLE>;
-  return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kSW - 1) / (G::TY * kSW));
-}
-template <int NU>
-dim3 sup_grid(int nx, int ny) {
-  using G = SGeomU<NU>;
+template <typename G>
+dim3 s_grid(int nx, int ny) {
   return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kSW - 1) / (G::TY * kSW));
 }
 
 template <int NU>
 void sdown_nu(const SOp &o, const float *b, float *rc, hipStream_t st) {
-  const Row8s none{};
-  k_sdown<NU, false><<<sdown_grid<NU, false>(o.nx, o.ny), 64 * kSW, 0, st>>>(
-      o, o, nullptr, nullptr, nullptr, none, 0, 0, b, nullptr, rc);
-}
-template <int NU>
-void sdown_couple_nu(const SOp &o, const SOp &ko, const double *v, const double *scale_j,
-                     const float *z, const Row8s &crow, int s, int i, float *b_out, float *rc,
-                     hipStream_t st) {
-  k_sdown<NU, true><<<sdown_grid<NU, true>(o.nx, o.ny), 64 * kSW, 0, st>>>(
-      o, ko, v, scale_j, z, crow, s, i, nullptr, b_out, rc);
+  k_sdown<NU><<<s_grid<SGeomD<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, rc);
 }
 template <int NU>
 void sup_nu(const SOp &o, const float *b, const float *ec, float *x, hipStream_t st) {
-  k_sup<NU><<<sup_grid<NU>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+  k_sup<NU><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
 }
 
 void scouple_launch(const KOpD &ko, const double *v, const double *scale_j, const float *z,
@@ -506,16 +498,6 @@ bool wsplit_ok(const OpView<float> &D) {
 void sdown(const OpView<float> &D, const float *interior, int nu, const float *b, float *rc,
            hipStream_t st) {
   IRK_S_NU(sdown_nu, make_sop(D, interior), b, rc, st);
-}
-
-void sdown_couple(const OpView<float> &D, const float *interior, const OpView<float> &K,
-                  const float *k_interior, int nu, const double *v, const double *scale_j,
-                  const float *z, const double *C, int s, int i, float *b_out, float *rc,
-                  hipStream_t st) {
-  Row8s crow{};
-  for (int k = 0; k < s; ++k) crow.c[k] = C[k];
-  IRK_S_NU(sdown_couple_nu, make_sop(D, interior), make_sop(K, k_interior), v, scale_j, z, crow,
-           s, i, b_out, rc, st);
 }
 
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
