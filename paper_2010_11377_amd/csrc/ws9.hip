@@ -121,6 +121,11 @@ __device__ __forceinline__ MidCo mid_coefs(const S9Op &o, const Place &p) {
     m.bot.a = side_coefs<2, 0>(o, p.fcol);
     m.bot.b = side_coefs<2, 2>(o, p.lcol);
   }
+  // lanes outside the grid relax with 1 / d = 0, which keeps them at zero
+  const int gxa = p.X0 + 2 * l9();
+  if (gxa < 0 || gxa >= o.nx) {
+    m.mid.a.inv = m.mid.b.inv = m.top.a.inv = m.top.b.inv = m.bot.a.inv = m.bot.b.inv = 0.0f;
+  }
   return m;
 }
 
@@ -138,8 +143,12 @@ __device__ __forceinline__ float offdiag_b(const C &c, const T9<R> &t, int r) {
          c[6] * t.xa[r + 1] + c[7] * t.xb[r + 1] + c[8] * nx9(t.xa[r + 1]);
 }
 
-// Coefficients of slot a / b in tile row r.
-template <bool BOUND, int R, int H, int TY>
+// Coefficients of slot a / b in tile row r.  YB: which tile rows lie
+// outside the grid (0 none, 1 the rows above the grid's first row, tile rows
+// < H, 2 those below its last row, tile rows >= H + TY): the grid height is a
+// multiple of TY, so these are the only cases, known at compile time; 3 is
+// both, a single tile row covering the grid).
+template <bool BOUND, int R, int H, int TY, int YB = 0>
 struct Ctx {
   const S9Op &o;
   const Place &p;
@@ -153,25 +162,31 @@ struct Ctx {
     if (!BOUND) return side_coefs<1, 1>(o, false);
     return r == H ? m.top.b : (r == H + TY - 1 ? m.bot.b : m.mid.b);
   }
+  // tile row r lies in the grid; rows outside are never updated and stay zero
+  __device__ __forceinline__ bool row_in(int r) const {
+    return (YB & 1 ? r >= H : true) && (YB & 2 ? r < H + TY : true);
+  }
+  __device__ __forceinline__ bool lane_in() const {
+    const int gxa = p.X0 + 2 * l9();
+    return !BOUND || (gxa >= 0 && gxa < o.nx);
+  }
 };
 
 // One colour half sweep over rows [M, R-M), Jacobi within the colour.
-template <bool BOUND, int R, int H, int TY, int M>
-__device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t, int color) {
-  const int gxa = cx.p.X0 + 2 * l9();
-  const bool inx = gxa >= 0 && gxa < cx.o.nx;
+template <bool BOUND, int R, int H, int TY, int YB, int M>
+__device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t, int color) {
   float pend = 0.0f;
 #pragma unroll
   for (int r = M; r < R - M; ++r) {
-    const int gy = cx.p.Y0 + r;
-    const bool in = !BOUND || (inx && gy >= 0 && gy < cx.o.ny);
-    float v;
-    if ((r & 1) == color) {
-      const Co c = cx.a(r);
-      v = (t.ba[r] - offdiag_a<R>(c, t, r)) * c.inv;
-    } else {
-      const Co c = cx.b(r);
-      v = (t.bb[r] - offdiag_b<R>(c, t, r)) * c.inv;
+    float v = 0.0f;
+    if (cx.row_in(r)) {
+      if ((r & 1) == color) {
+        const Co c = cx.a(r);
+        v = (t.ba[r] - offdiag_a<R>(c, t, r)) * c.inv;
+      } else {
+        const Co c = cx.b(r);
+        v = (t.bb[r] - offdiag_b<R>(c, t, r)) * c.inv;
+      }
     }
     if (r > M) {  // row r-1 is no longer read by this half sweep
       if (((r - 1) & 1) == color)
@@ -179,7 +194,7 @@ __device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY> &cx, T9<R> &
       else
         t.xb[r - 1] = pend;
     }
-    pend = in ? v : 0.0f;
+    pend = v;
   }
   constexpr int rl = R - M - 1;
   if ((rl & 1) == color)
@@ -188,8 +203,8 @@ __device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY> &cx, T9<R> &
     t.xb[rl] = pend;
 }
 
-template <bool BOUND, int R, int H, int TY, int NU>
-__device__ __forceinline__ void s9_pre(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t) {
+template <bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_pre(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     // from x = 0 the first colour-0 half sweep is x = b / d (b is zero
@@ -202,37 +217,37 @@ __device__ __forceinline__ void s9_pre(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t)
       t.xa[r] = 0.0f;
     }
   }
-  s9_sweep<BOUND, R, H, TY, 1>(cx, t, 1);
+  s9_sweep<BOUND, R, H, TY, YB, 1>(cx, t, 1);
   if (NU >= 2) {
-    s9_sweep<BOUND, R, H, TY, 2>(cx, t, 0);
-    s9_sweep<BOUND, R, H, TY, 3>(cx, t, 1);
+    s9_sweep<BOUND, R, H, TY, YB, 2>(cx, t, 0);
+    s9_sweep<BOUND, R, H, TY, YB, 3>(cx, t, 1);
   }
   if (NU >= 3) {
-    s9_sweep<BOUND, R, H, TY, 4>(cx, t, 0);
-    s9_sweep<BOUND, R, H, TY, 5>(cx, t, 1);
+    s9_sweep<BOUND, R, H, TY, YB, 4>(cx, t, 0);
+    s9_sweep<BOUND, R, H, TY, YB, 5>(cx, t, 1);
   }
 }
 
 // Post-smoothing in the reverse colour order (colour 1 first), from x exact
 // on the whole tile (the stored pre-smoothed x plus the coarse correction).
-template <bool BOUND, int R, int H, int TY, int NU>
-__device__ __forceinline__ void s9_post(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t) {
-  s9_sweep<BOUND, R, H, TY, 1>(cx, t, 1);
-  s9_sweep<BOUND, R, H, TY, 2>(cx, t, 0);
+template <bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_post(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t) {
+  s9_sweep<BOUND, R, H, TY, YB, 1>(cx, t, 1);
+  s9_sweep<BOUND, R, H, TY, YB, 2>(cx, t, 0);
   if (NU >= 2) {
-    s9_sweep<BOUND, R, H, TY, 3>(cx, t, 1);
-    s9_sweep<BOUND, R, H, TY, 4>(cx, t, 0);
+    s9_sweep<BOUND, R, H, TY, YB, 3>(cx, t, 1);
+    s9_sweep<BOUND, R, H, TY, YB, 4>(cx, t, 0);
   }
   if (NU >= 3) {
-    s9_sweep<BOUND, R, H, TY, 5>(cx, t, 1);
-    s9_sweep<BOUND, R, H, TY, 6>(cx, t, 0);
+    s9_sweep<BOUND, R, H, TY, YB, 5>(cx, t, 1);
+    s9_sweep<BOUND, R, H, TY, YB, 6>(cx, t, 0);
   }
 }
 
 // rc = R (b - D x), sum over 2 x 2 cells: both slots of one lane, two rows.
 // Writes the coarse nodes of this wave's output rows and lanes.
-template <bool BOUND, int R, int H, int TY>
-__device__ __forceinline__ void s9_restrict(const Ctx<BOUND, R, H, TY> &cx, const T9<R> &t,
+template <bool BOUND, int R, int H, int TY, int YB>
+__device__ __forceinline__ void s9_restrict(const Ctx<BOUND, R, H, TY, YB> &cx, const T9<R> &t,
                                             float *__restrict__ rcoarse) {
   const S9Op &o = cx.o;
   const Place &p = cx.p;
@@ -240,20 +255,22 @@ __device__ __forceinline__ void s9_restrict(const Ctx<BOUND, R, H, TY> &cx, cons
   const int gxa = p.X0 + 2 * lane;
   const int ncx = o.nx / 2, ncy = o.ny / 2;
   const int I = gxa >> 1;
-  const bool inx = gxa >= 0 && gxa < o.nx;
+  const bool inx = cx.lane_in();
   const bool lane_out = lane >= p.lo && lane < p.hi && gxa >= p.OXn && I < ncx;
 #pragma unroll
   for (int r = H; r < R - H; r += 2) {
     float sum = 0.0f;
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
-      const int rr = r + d, gy = p.Y0 + rr;
+      const int rr = r + d;
+      if (!cx.row_in(rr)) continue;
       const Co ca = cx.a(rr), cb = cx.b(rr);
       const float ra = t.ba[rr] - ca.c[4] * t.xa[rr] - offdiag_a<R>(ca, t, rr);
       const float rb = t.bb[rr] - cb.c[4] * t.xb[rr] - offdiag_b<R>(cb, t, rr);
-      const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
-      sum += in ? ra + rb : 0.0f;
+      sum += ra + rb;
     }
+    // an outside node next to an inside one has a nonzero residual
+    if (!inx) sum = 0.0f;
     const int gy0 = p.Y0 + r, J = gy0 >> 1;
     if (lane_out && gy0 >= p.OYn && J < ncy) rcoarse[(size_t)J * ncx + I] = sum;
   }
@@ -319,6 +336,14 @@ __device__ __forceinline__ bool boundary_tile(const Place &p, int R, int nx, int
   return !(p.X0 >= 1 && p.Y0 >= 1 && p.X0 + 128 <= nx - 1 && p.Y0 + R <= ny - 1);
 }
 
+template <bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_down_tile(const S9Op &o, const Place &p, const MidCo &m,
+                                             T9<R> &t, float *__restrict__ rc) {
+  const Ctx<BOUND, R, H, TY, YB> cx{o, p, m};
+  s9_pre<BOUND, R, H, TY, YB, NU>(cx, t);
+  s9_restrict<BOUND, R, H, TY, YB>(cx, t, rc);
+}
+
 // Pre-smoothing from zero and rc = R (b - D x); the pre-smoothed x of the
 // output region goes to xpre for the up pass.
 template <int NU, int TY>
@@ -332,15 +357,17 @@ __global__ void __launch_bounds__(64 * kW9)
   T9<R> t;
   s9_load<R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
   if (!boundary_tile(p, R, o.nx, o.ny)) {
-    const MidCo m{};
-    const Ctx<false, R, H, TY> cx{o, p, m};
-    s9_pre<false, R, H, TY, NU>(cx, t);
-    s9_restrict<false, R, H, TY>(cx, t, rc);
+    s9_down_tile<false, R, H, TY, 0, NU>(o, p, MidCo{}, t, rc);
   } else {
     const MidCo m = mid_coefs(o, p);
-    const Ctx<true, R, H, TY> cx{o, p, m};
-    s9_pre<true, R, H, TY, NU>(cx, t);
-    s9_restrict<true, R, H, TY>(cx, t, rc);
+    if (p.top && p.bot)
+      s9_down_tile<true, R, H, TY, 3, NU>(o, p, m, t, rc);
+    else if (p.top)
+      s9_down_tile<true, R, H, TY, 1, NU>(o, p, m, t, rc);
+    else if (p.bot)
+      s9_down_tile<true, R, H, TY, 2, NU>(o, p, m, t, rc);
+    else
+      s9_down_tile<true, R, H, TY, 0, NU>(o, p, m, t, rc);
   }
   const int lane = l9(), gxa = p.X0 + 2 * lane;
   if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
@@ -354,8 +381,8 @@ __global__ void __launch_bounds__(64 * kW9)
 }
 
 // x = xpre + P e_c, then the post-smoothing.
-template <bool BOUND, int R, int H, int TY, int NU>
-__device__ __forceinline__ void s9_up_body(const Ctx<BOUND, R, H, TY> &cx, T9<R> &t,
+template <bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_up_body(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t,
                                            const float (&cr)[R / 2 + 3]) {
   const S9Op &o = cx.o;
   // fine column 2I takes 3/4 of coarse column I and 1/4 of I-1, column 2I+1
@@ -363,23 +390,32 @@ __device__ __forceinline__ void s9_up_body(const Ctx<BOUND, R, H, TY> &cx, T9<R>
   // takes pw of its coarse node (its second coarse node is outside the grid,
   // where cr and the neighbour lanes hold zero)
   const int gxa = cx.p.X0 + 2 * l9();
-  const bool inx = gxa >= 0 && gxa < o.nx;
-  const float wxa = gxa == 0 ? o.pw : 0.75f;
-  const float wxb = gxa + 2 == o.nx ? o.pw : 0.75f;
+  const bool inx = cx.lane_in();
+  // lanes outside the grid take no correction
+  const float wxa = !inx ? 0.0f : (gxa == 0 ? o.pw : 0.75f);
+  const float wxb = !inx ? 0.0f : (gxa + 2 == o.nx ? o.pw : 0.75f);
+  const float wq = !inx ? 0.0f : 0.25f;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    if (!cx.row_in(r)) continue;
     const int gy = cx.p.Y0 + r;
-    const bool in = !BOUND || (inx && gy >= 0 && gy < o.ny);
     const float wy = (gy == 0 || gy == o.ny - 1) ? o.pw : 0.75f;
     const float cj = cr[r / 2 + 1];
     const float cn = cr[(r & 1) ? r / 2 + 2 : r / 2];
     const float ya = wy * cj + 0.25f * cn;
     const float yp = wy * pv9(cj) + 0.25f * pv9(cn);
     const float yn = wy * nx9(cj) + 0.25f * nx9(cn);
-    t.xa[r] += in ? wxa * ya + 0.25f * yp : 0.0f;
-    t.xb[r] += in ? wxb * ya + 0.25f * yn : 0.0f;
+    t.xa[r] += wxa * ya + wq * yp;
+    t.xb[r] += wxb * ya + wq * yn;
   }
-  s9_post<BOUND, R, H, TY, NU>(cx, t);
+  s9_post<BOUND, R, H, TY, YB, NU>(cx, t);
+}
+
+template <bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_up_tile(const S9Op &o, const Place &p, const MidCo &m,
+                                           T9<R> &t, const float (&cr)[R / 2 + 3]) {
+  const Ctx<BOUND, R, H, TY, YB> cx{o, p, m};
+  s9_up_body<BOUND, R, H, TY, YB, NU>(cx, t, cr);
 }
 
 template <int NU, int TY>
@@ -405,13 +441,17 @@ __global__ void __launch_bounds__(64 * kW9)
     }
   }
   if (!boundary_tile(p, R, o.nx, o.ny)) {
-    const MidCo m{};
-    const Ctx<false, R, H, TY> cx{o, p, m};
-    s9_up_body<false, R, H, TY, NU>(cx, t, cr);
+    s9_up_tile<false, R, H, TY, 0, NU>(o, p, MidCo{}, t, cr);
   } else {
     const MidCo m = mid_coefs(o, p);
-    const Ctx<true, R, H, TY> cx{o, p, m};
-    s9_up_body<true, R, H, TY, NU>(cx, t, cr);
+    if (p.top && p.bot)
+      s9_up_tile<true, R, H, TY, 3, NU>(o, p, m, t, cr);
+    else if (p.top)
+      s9_up_tile<true, R, H, TY, 1, NU>(o, p, m, t, cr);
+    else if (p.bot)
+      s9_up_tile<true, R, H, TY, 2, NU>(o, p, m, t, cr);
+    else
+      s9_up_tile<true, R, H, TY, 0, NU>(o, p, m, t, cr);
   }
   const int gxa = p.X0 + 2 * lane;
   if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
