@@ -126,6 +126,13 @@ typedef struct {
                       lowers the per-kernel launch cost; 0: direct launches.
                       Both run the same kernels in the same order, so the
                       results are identical. */
+  double coarse_ratio; /* end of a block's V-cycle: the first level l whose
+                      block S_l + tau_i K_l has tau_i max_p (K_l)_pp / (S_l)_pp
+                      <= coarse_ratio (S_l, K_l the Galerkin mass and
+                      stiffness operators of level l, S_0 = M) runs its pre-
+                      and post-smoothing with no coarse correction, and the
+                      levels below it are skipped for that block.  0: every
+                      cycle goes down to the coarsest level (solved exactly). */
 } irk_options;
 
 typedef struct {
@@ -139,7 +146,7 @@ typedef struct {
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
  * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR,
- * graphs 1. */
+ * graphs 1, coarse_ratio 2. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.

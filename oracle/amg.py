@@ -32,7 +32,15 @@ reading taken for the structured finite-difference grids of Sec. 3:
   a colour (for five-point operators that is Gauss-Seidel), ``nu`` sweeps of
   colours 0 then 1 before the coarse correction and ``nu`` sweeps of colours
   1 then 0 after it;
-* one V-cycle from a zero initial guess per block.
+* one V-cycle from a zero initial guess per block;
+* optional early end of the cycle (``coarse_ratio`` > 0): the first level
+  whose block is dominated by its mass part, tau_i max_p (K_l)_pp / (S_l)_pp
+  <= coarse_ratio, runs its pre- and post-smoothing with no coarse
+  correction (the levels below it are not visited).  Such a block is close
+  to its mass matrix, which the smoother alone reduces well, so the coarser
+  levels add little; in algebraic multigrid terms the hierarchy of that
+  block stops where the operator stops being dominated by the stiffness
+  part.
 
 Parity of this reading against the paper is unpinned (the paper gives no AMG
 details); the tests pin the code against closed-form Galerkin stencils, a
@@ -130,7 +138,16 @@ def relax(D, diag, col, b, x, colour):
     return x
 
 
-def vcycle(levels, tau, b, nu=2, level=0):
+def ends_cycle(S, Kl, tau, coarse_ratio):
+    """True if the level's block S_l + tau K_l ends the V-cycle:
+    tau max_p (K_l)_pp / (S_l)_pp <= coarse_ratio (never for coarse_ratio 0
+    or tau <= 0)."""
+    if coarse_ratio <= 0.0 or tau <= 0.0:
+        return False
+    return tau * np.max(Kl.diagonal() / S.diagonal()) <= coarse_ratio
+
+
+def vcycle(levels, tau, b, nu=2, level=0, coarse_ratio=0.0):
     """One V(nu, nu)-cycle from x = 0 for D_l = S_l + tau K_l."""
     nx, ny, S, Kl, P, R = levels[level]
     D = (S + tau * Kl).tocsr()
@@ -142,8 +159,9 @@ def vcycle(levels, tau, b, nu=2, level=0):
     for _ in range(nu):
         x = relax(D, diag, col, b, x, 0)
         x = relax(D, diag, col, b, x, 1)
-    rc = R @ (b - D @ x)
-    x = x + P @ vcycle(levels, tau, rc, nu, level + 1)
+    if not ends_cycle(S, Kl, tau, coarse_ratio):
+        rc = R @ (b - D @ x)
+        x = x + P @ vcycle(levels, tau, rc, nu, level + 1, coarse_ratio)
     for _ in range(nu):
         x = relax(D, diag, col, b, x, 1)
         x = relax(D, diag, col, b, x, 0)
@@ -151,7 +169,7 @@ def vcycle(levels, tau, b, nu=2, level=0):
 
 
 def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=None,
-                                interp="linear"):
+                                interp="linear", coarse_ratio=0.0):
     """``z ~= P^-1 v`` by block substitution (Sec. 4.2) with one V-cycle per
     diagonal block ``M + h A~_jj K`` instead of an exact solve (M = I if
     None)."""
@@ -171,5 +189,5 @@ def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=
         for k in range(s):
             if k != j and At[j, k] != 0.0:
                 rhs -= h * At[j, k] * (K @ z[k])
-        z[j] = vcycle(levels, h * At[j, j], rhs, nu)
+        z[j] = vcycle(levels, h * At[j, j], rhs, nu, coarse_ratio=coarse_ratio)
     return z

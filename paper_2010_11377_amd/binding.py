@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("coarse_max", ctypes.c_int), ("vcycles", ctypes.c_int),
                 ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("side", ctypes.c_int),
-                ("interp", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("interp", ctypes.c_int), ("graphs", ctypes.c_int),
+                ("coarse_ratio", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

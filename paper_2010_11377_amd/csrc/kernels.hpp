@@ -48,7 +48,7 @@ struct TailDesc {
   const T *arr[kTailLevels];
   T pw[kTailLevels];  // prolongation boundary weight of level l (see OpView)
   T pa = T(0.75), pn = T(0.25);  // parent / next-node prolongation weights (see OpView)
-  const T *CinvT;
+  const T *CinvT;  // null: the coarsest level returns x = 0 (the cycle ends one level up)
 };
 
 // Scalars the Krylov kernels read from device memory so that a whole

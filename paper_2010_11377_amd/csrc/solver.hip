@@ -83,6 +83,9 @@ struct irk_solver {
   bool const_mode = false, symmetric = false;
   int nlev = 0, ncoarse = 0;
   int lt = 0;  // first level handled by the single-workgroup tail kernel
+  // per stage: the level that ends its V-cycle (pre- and post-smoothing, no
+  // coarse correction); nlev - 1 when the cycle reaches the coarsest level
+  std::vector<int> cycle_end;
   std::vector<int> lnx, lny;
 
   // mass matrix (Sec. 3.1: M_kl = integral of phi_k phi_l); none means M = I
@@ -290,6 +293,27 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   for (int l = 0; l < L && cm; ++l) cm = irk::classify(Sl[l], 1e-12, tmp) && irk::classify(Kl[l], 1e-12, tmp);
   S->const_mode = cm;
   S->nlev = L;
+  // end of each block's cycle: the first level with tau_i max_p (K_l)_pp /
+  // (S_l)_pp <= coarse_ratio
+  S->cycle_end.assign(S->s, L - 1);
+  if (S->opt.coarse_ratio > 0.0) {
+    std::vector<double> ratio(L, 0.0);
+    for (int l = 0; l + 1 < L; ++l) {
+      const size_t n = (size_t)Sl[l].nx * Sl[l].ny;
+      for (size_t q = 0; q < n; ++q) {
+        const double sd = Sl[l].c[4][q], kd = Kl[l].c[4][q];
+        ratio[l] = sd > 0.0 ? std::max(ratio[l], kd / sd) : INFINITY;
+      }
+    }
+    for (int i = 0; i < S->s; ++i) {
+      if (!(S->tau[i] > 0.0)) continue;
+      for (int l = 0; l + 1 < L; ++l)
+        if (S->tau[i] * ratio[l] <= S->opt.coarse_ratio) {
+          S->cycle_end[i] = l;
+          break;
+        }
+    }
+  }
   S->ncoarse = (int)ncoarse;
   S->lnx.clear();
   S->lny.clear();
@@ -530,14 +554,22 @@ void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, 
 
 // One V(nu, nu)-cycle for the stage-i block, x ~= D_i^-1 b on the finest
 // level (Sec. 4.2): fused down passes to the tail level, the tail in one
-// workgroup, fused up passes back.
+// workgroup, fused up passes back.  The cycle ends at level E = cycle_end[i]:
+// E takes its smoothing with a zero coarse correction (an up pass from the
+// zero vector, or a tail whose coarsest level returns zero).
 template <typename T>
 void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   hipStream_t st = S->stream;
-  const int nu = S->opt.nu_pre, lt = S->lt, L = S->nlev;
+  const int nu = S->opt.nu_pre, L = S->nlev;
+  const int E = S->cycle_end[i];
+  const bool ends = E < L - 1;          // the cycle stops above the coarsest level
+  const bool tail = E >= S->lt;         // ... at or below the tail's first level
+  const int lt = tail ? S->lt : E + 1;  // levels run by the fused passes: 0 .. lt-1
+  const int Lt = ends ? E + 2 : L;      // tail levels lt .. Lt-1; if ends, Lt-1 returns zero
   const size_t es = sizeof(T);
   auto bl = [&](int l) -> const T * { return l == 0 ? b : lev_b<T>(S, l); };
   auto xl = [&](int l) -> T * { return l == 0 ? x : lev_x<T>(S, l); };
+  const T *zero = reinterpret_cast<const T *>(S->zero);
   for (int l = finest_down_done ? 1 : 0; l < lt; ++l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
@@ -546,9 +578,9 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
     prof_end(S, t);
   }
-  {
+  if (tail) {
     irk::TailDesc<T> td{};
-    td.nlev = L - lt;
+    td.nlev = Lt - lt;
     size_t off = 0, words = 0;
     for (int k = 0; k < td.nlev; ++k) {
       const int l = lt + k;
@@ -556,7 +588,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
       td.ny[k] = S->lny[l];
       td.off[k] = off;
       off += 2 * (size_t)S->lnx[l] * S->lny[l];
-      if (l < L - 1) {
+      if (l < Lt - 1) {
         const DevOp<T> &D = Dops<T>(S)[i][l];
         td.cls[k] = D.cls;
         td.arr[k] = D.arr;
@@ -567,9 +599,10 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
       }
     }
     td.off[td.nlev] = off;
-    td.CinvT = Cinv<T>(S, i);
+    // a cycle that ends inside the tail: its coarsest level returns zero
+    td.CinvT = ends ? nullptr : Cinv<T>(S, i);
     const size_t ntop = (size_t)S->lnx[lt] * S->lny[lt];
-    words += 2 * ntop + (size_t)S->ncoarse * S->ncoarse;
+    words += 2 * ntop + (ends ? 0 : (size_t)S->ncoarse * S->ncoarse);
     ProfTok t = prof_begin(S, IRK_KC_VTAIL, (double)words * es);
     bool done = false;
     if constexpr (std::is_same_v<T, float>) {
@@ -586,7 +619,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     const size_t n = (size_t)D.nx * D.ny;
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID_UP,
                            (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
-    up_pass<T>(D, nu, bl(l), lev_x<T>(S, l + 1), lev_p<T>(S, l), xl(l), st);
+    up_pass<T>(D, nu, bl(l), l == E ? zero : lev_x<T>(S, l + 1), lev_p<T>(S, l), xl(l), st);
     prof_end(S, t);
   }
 }
@@ -1018,6 +1051,8 @@ bool valid_options(const irk_options &o, std::string &err) {
   if (o.interp != IRK_INTERP_LINEAR && o.interp != IRK_INTERP_CONSTANT)
     return err = "interp must be IRK_INTERP_LINEAR or IRK_INTERP_CONSTANT", false;
   if (o.graphs != 0 && o.graphs != 1) return err = "graphs must be 0 or 1", false;
+  if (!(o.coarse_ratio >= 0.0) || !std::isfinite(o.coarse_ratio))
+    return err = "coarse_ratio must be finite and >= 0", false;
   if (o.side == IRK_LEFT && o.precision != IRK_FP64)
     return err = "left preconditioning needs precision IRK_FP64", false;
   return true;
@@ -1063,6 +1098,7 @@ void irk_default_options(irk_options *o) {
   o->side = IRK_RIGHT;
   o->interp = IRK_INTERP_LINEAR;
   o->graphs = 1;
+  o->coarse_ratio = 2.0;
 }
 
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {

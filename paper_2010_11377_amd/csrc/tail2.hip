@@ -86,7 +86,7 @@ struct T2Desc {
   const float *arr[kTailLevels];
   float pw[kTailLevels];
   float pa, pn;  // prolongation weights from the own and the next coarse node
-  const float *CinvT;
+  const float *CinvT;  // null: the coarsest level returns x = 0
   int store_off[kTailLevels];  // LDS offset of level l's parked x (and b for l > 0)
 };
 
@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(kT2Threads)
 #pragma unroll
       for (int k = 0; k < kT2CiPer; ++k) {
         const int q = q0 + k * (kT2Threads - 64);
-        v[k] = q < nc * nc ? td.CinvT[q] : 0.0f;
+        v[k] = q < nc * nc && td.CinvT ? td.CinvT[q] : 0.0f;
       }
 #pragma unroll
       for (int k = 0; k < kT2CiPer; ++k) {
@@ -712,7 +712,8 @@ __global__ void __launch_bounds__(kT2Threads)
       const int row = threadIdx.x;
       if (row < nc) {
         float acc = 0.0f;
-        for (int col = 0; col < nc; ++col) acc += A[col * nc + row] * bc[col];
+        if (td.CinvT)
+          for (int col = 0; col < nc; ++col) acc += A[col * nc + row] * bc[col];
         if (L == 1)
           x_top[row] = acc;
         else
@@ -740,7 +741,8 @@ __global__ void __launch_bounds__(kT2Threads)
     for (int q = threadIdx.x; q < nb * nc; q += kT2Threads) {
       const int row = q % nc, cb = q / nc;
       float acc = 0.0f;
-      for (int col = cb; col < nc; col += nb) acc += td.CinvT[(size_t)col * nc + row] * bc[col];
+      if (td.CinvT)
+        for (int col = cb; col < nc; col += nb) acc += td.CinvT[(size_t)col * nc + row] * bc[col];
       red[q] = acc;
     }
     __syncthreads();

@@ -466,7 +466,8 @@ __global__ void __launch_bounds__(kTailThreads)
     for (int t = threadIdx.x; t < nb * n; t += kTailThreads) {
       const int r = t % n, cb = t / n;
       T acc = T(0);
-      for (int c = cb; c < n; c += nb) acc += td.CinvT[(size_t)c * n + r] * sb[c];
+      if (td.CinvT)
+        for (int c = cb; c < n; c += nb) acc += td.CinvT[(size_t)c * n + r] * sb[c];
       red[t] = acc;
     }
     __syncthreads();

@@ -1,0 +1,136 @@
+"""GPU tests of the early end of the V-cycle (option coarse_ratio): the first
+level l of block i with tau_i max_p (K_l)_pp / (S_l)_pp <= coarse_ratio runs
+its pre- and post-smoothing with no coarse correction.
+
+* one preconditioner application against the oracle's V-cycle with the same
+  rule, with the cycle ending on the finest level, on a multi-workgroup mid
+  level, on the tail's first level and inside the tail, FP32 and FP64, heat,
+  double glazing and linear elements;
+* the rule off (coarse_ratio 0) reproduces the full cycle;
+* FGMRES iteration counts of the heat benchmark shape (Gauss-Legendre 7,
+  h_t = 1e-3) are the same with and without the early end (printed), and the
+  steps agree with the oracle's exact steps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.amg import apply_vcycle_preconditioner, hierarchy
+from oracle.fem import p1_heat as oracle_p1
+from oracle.ldu import coefficient_matrix
+from oracle.operators import double_glazing, heat_K
+from oracle.step import EigenStepper, run_steps
+from oracle.tableau import tableau as oracle_tableau
+from paper_2010_11377_amd import problems, tableaux, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _level_ratios(Ko, n, Mo=None):
+    """max_p (K_l)_pp / (S_l)_pp per level of the oracle hierarchy."""
+    return [float(np.max(Kl.diagonal() / S.diagonal()))
+            for (_, _, S, Kl, P, _) in hierarchy(Ko, n, n, 64, Mo) if P is not None]
+
+
+# (problem, n, h, precision, level the cycle of every block ends on)
+CASES = [("heat", 256, 1e-3, "mixed", 0), ("heat", 256, 1e-3, "fp64", 0),
+         ("heat", 512, 1e-3, "mixed", 2), ("heat", 512, 1e-3, "fp64", 2),
+         ("heat", 512, 1e-3, "mixed", 3), ("heat", 512, 1e-3, "mixed", 4),
+         ("heat", 256, 1e-2, "fp64", 3),
+         ("dg", 128, 5e-2, "mixed", 1), ("dg", 128, 5e-2, "fp64", 2),
+         ("p1", 256, 1e-3, "mixed", 3)]
+
+
+@pytest.mark.parametrize("problem,n,h,precision,level", CASES)
+def test_preconditioner_with_cycle_end_matches_oracle(dev, problem, n, h, precision, level):
+    from paper_2010_11377_amd.solver import IRKSolver
+    say("case cycle end %s n=%d h=%g %s level %d" % (problem, n, h, precision, level))
+    s = 3
+    A, b, c = tableaux.tableau("radau_iia", s)
+    Ao = oracle_tableau("radau_iia", s)[0]
+    At = coefficient_matrix(Ao, "LD")
+    Mp = Mo = None
+    if problem == "heat":
+        Kp, Ko = problems.heat(n), heat_K(n)
+    elif problem == "dg":
+        Kp, Ko = problems.double_glazing(n, 0.005)[:3], double_glazing(n, 0.005)[0]
+    else:
+        Mp, Kp = problems.p1_heat(n)
+        Mo, Ko = oracle_p1(n)
+    r = _level_ratios(Ko, n, Mo)
+    assert r == sorted(r, reverse=True)     # the ratio falls with the level
+    # a coarse_ratio that ends every block's cycle exactly on `level`
+    taus = [h * At[i, i] for i in range(s)]
+    lo = max(t * r[level] for t in taus)
+    hi = min(t * r[level - 1] for t in taus) if level > 0 else np.inf
+    assert lo < hi, (lo, hi)
+    cr = lo * 1.001 if hi == np.inf else np.sqrt(lo * hi)
+    S = IRKSolver(A, b, c, Kp, h, (n, n), precision=precision, M=Mp, coarse_ratio=cr,
+                  device=dev)
+    v = np.random.default_rng(21).standard_normal(s * n * n)
+    z = S.apply_preconditioner(torch.tensor(v, dtype=torch.float64, device=dev)).cpu().numpy()
+    S.close()
+    ref = apply_vcycle_preconditioner(At, Ko, h, v.reshape(s, -1), n, n, M=Mo,
+                                      coarse_ratio=cr).ravel()
+    full = apply_vcycle_preconditioner(At, Ko, h, v.reshape(s, -1), n, n, M=Mo).ravel()
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    gap = np.linalg.norm(full - ref) / np.linalg.norm(ref)
+    say("  coarse_ratio %.3g: rel err %.2e (full cycle differs by %.2e)" % (cr, err, gap))
+    assert err < (1e-11 if precision == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_rule_off_is_the_full_cycle(dev, precision):
+    from paper_2010_11377_amd.solver import IRKSolver
+    n, h = 256, 1e-3
+    A, b, c = tableaux.tableau("gauss", 3)
+    S = IRKSolver(A, b, c, problems.heat(n), h, (n, n), precision=precision, coarse_ratio=0.0,
+                  device=dev)
+    v = np.random.default_rng(22).standard_normal(3 * n * n)
+    z = S.apply_preconditioner(torch.tensor(v, dtype=torch.float64, device=dev)).cpu().numpy()
+    S.close()
+    At = coefficient_matrix(oracle_tableau("gauss", 3)[0], "LD")
+    ref = apply_vcycle_preconditioner(At, heat_K(n), h, v.reshape(3, -1), n, n).ravel()
+    assert np.linalg.norm(z - ref) <= (1e-11 if precision == "fp64" else 2e-5) * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_benchmark_shape_iterations_unchanged(dev, precision):
+    from paper_2010_11377_amd.solver import IRKSolver
+    n, h, steps = 1024, 1e-3, 3
+    A, b, c = tableaux.tableau("gauss", 7)
+    u0 = workloads.fourier_modes(n, seed=0)
+    out = {}
+    for cr in (0.0, None):
+        S = IRKSolver(A, b, c, problems.heat(n), h, (n, n), precision=precision,
+                      coarse_ratio=cr, device=dev)
+        u = torch.tensor(u0, dtype=torch.float64, device=dev)
+        its = []
+        for _ in range(steps):
+            u = S.step(u)
+            its.append(S.last_stats.iters)
+        out[cr] = (its, u.cpu().numpy(), S.options.coarse_ratio)
+        S.close()
+    say("case GL7 1024^2 %s: iterations full cycle %s, early end (ratio %g) %s" % (
+        precision, out[0.0][0], out[None][2], out[None][0]))
+    assert out[None][0] == out[0.0][0]
+    Ao, bo, _ = oracle_tableau("gauss", 7)
+    ref = run_steps(EigenStepper(Ao, bo, heat_K(n), h), u0, steps)
+    err = np.linalg.norm(out[None][1] - ref) / np.linalg.norm(ref)
+    say("  rel err vs oracle %.2e" % err)
+    assert err < 1e-8

@@ -49,11 +49,12 @@ def test_constant_interp_preconditioner_matches_oracle(dev, which, n, h, precisi
     v = np.random.default_rng(12).standard_normal((3, n * n))
     z = S.apply_preconditioner(torch.tensor(v.ravel(), dtype=torch.float64, device=dev))
     z = z.cpu().numpy().reshape(3, n * n)
+    cr = S.options.coarse_ratio
     S.close()
     Ko = double_glazing(n, 0.005)[0] if which == "dg" else heat_K(n)
     Ao, _, _ = oracle_tableau("radau_iia", 3)
     ref = apply_vcycle_preconditioner(coefficient_matrix(Ao, "LD"), Ko, h, v, n, n,
-                                      interp="constant")
+                                      interp="constant", coarse_ratio=cr)
     err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
     say("  rel err %.2e" % err)
     assert err < (1e-11 if precision == "fp64" else 2e-5)

@@ -97,6 +97,7 @@ def test_mass_preconditioner_matches_oracle(dev, n, precision, coarse_max):
     v = np.random.default_rng(12).standard_normal((3, n * n))
     z = S.apply_preconditioner(torch.tensor(v.ravel(), dtype=torch.float64, device=dev))
     z = z.cpu().numpy().reshape(3, n * n)
+    cr = S.options.coarse_ratio
     S.close()
     Mo, Ko = oracle_p1(n)
     Ao, _, _ = oracle_tableau("radau_iia", 3)
@@ -104,7 +105,8 @@ def test_mass_preconditioner_matches_oracle(dev, n, precision, coarse_max):
     if coarse_max >= n * n:
         ref = apply_inverse(At, Ko, h, v, M=Mo)
     else:
-        ref = apply_vcycle_preconditioner(At, Ko, h, v, n, n, coarse_max=coarse_max, M=Mo)
+        ref = apply_vcycle_preconditioner(At, Ko, h, v, n, n, coarse_max=coarse_max, M=Mo,
+                                          coarse_ratio=cr)
     err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
     say("  rel err %.2e" % err)
     assert err < (1e-11 if precision == "fp64" else 2e-5)

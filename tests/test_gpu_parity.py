@@ -163,7 +163,8 @@ def test_vcycle_preconditioner_matches_oracle(dev, problem, nx, ny, precision):
     z = S.apply_preconditioner(T(v, dev)).cpu().numpy()
     Ao = oracle_tableau("radau_iia", s)[0]
     ref = apply_vcycle_preconditioner(coefficient_matrix(Ao, "LD"), Ko, h, v.reshape(s, -1),
-                                      nx, ny, nu=2, coarse_max=64).ravel()
+                                      nx, ny, nu=2, coarse_max=64,
+                                      coarse_ratio=S.options.coarse_ratio).ravel()
     err = rel(z, ref)
     say("  rel err", err)
     assert err < (1e-11 if precision == "fp64" else 2e-5)

@@ -21,7 +21,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from oracle.amg import (apply_vcycle_preconditioner, colours, hierarchy, prolongation,
+from oracle.amg import (apply_vcycle_preconditioner, colours, ends_cycle, hierarchy, prolongation,
                         restriction, vcycle)
 from oracle.ldu import coefficient_matrix
 from oracle.operators import double_glazing, heat_K, kappa_diffusion_K
@@ -252,3 +252,74 @@ def test_constant_interpolation_keeps_m_matrices_and_converges():
         factors[interp] = (all(mm), f)
     assert factors["constant"][0] and factors["constant"][1] < 0.75
     assert not factors["linear"][0] and factors["linear"][1] > 1.0
+
+
+# ---- early end of the cycle (coarse_ratio) ---------------------------------
+
+def _heat_ratio_closed_forms(n):
+    """tau-free ratios max_p (K_l)_pp / (S_l)_pp on levels 0 and 1 of the FD
+    heat hierarchy, from the closed-form stencils above: level 0 K = 4 h^-2,
+    S = 1; level 1 interior K = 3 h^-2, S = 1.5^2; edge K = 19/6 h^-2,
+    S = 1.5 (17/12); corner K = 119/36 h^-2, S = (17/12)^2."""
+    h2 = float(n + 1) ** 2
+    r0 = 4.0 * h2
+    r1 = h2 * max(3.0 / 2.25, (19.0 / 6.0) / (1.5 * 17.0 / 12.0), (119.0 / 36.0) / (17.0 / 12.0) ** 2)
+    return r0, r1
+
+
+def test_cycle_end_rule_closed_form():
+    n, tau = 16, 1e-3
+    lev = hierarchy(heat_K(n), n, n, coarse_max=1)
+    r0, r1 = _heat_ratio_closed_forms(n)
+    (_, _, S0, K0) = lev[0][:4]
+    (_, _, S1, K1) = lev[1][:4]
+    for S, Kl, r in ((S0, K0, r0), (S1, K1, r1)):
+        assert ends_cycle(S, Kl, tau, tau * r * (1 + 1e-9))
+        assert not ends_cycle(S, Kl, tau, tau * r * (1 - 1e-9))
+    assert not ends_cycle(S0, K0, tau, 0.0) and not ends_cycle(S0, K0, 0.0, 1e9)
+
+
+def test_cycle_ending_on_level_1_equals_dense_formulation():
+    """The cycle that ends on level 1 is the V-cycle whose level-1 coarse
+    correction is zero: B_1 = (I - post_1 pre_1) D_1^-1."""
+    n, tau, nu = 16, 3e-2, 2
+    lev = hierarchy(heat_K(n), n, n, coarse_max=16)
+    r0, r1 = _heat_ratio_closed_forms(n)
+    ratio = tau * 0.5 * (r0 + r1)           # between the two levels' ratios
+    b = np.random.default_rng(18).standard_normal(n * n)
+    x = vcycle(lev, tau, b, nu, coarse_ratio=ratio)
+
+    def dense(l):
+        nx, ny, S, K, P, R = lev[l]
+        D = (S + tau * K).toarray()
+        m = D.shape[0]
+        col = colours(nx, ny)
+        G = [np.eye(m) - np.diag((col == c) / np.diag(D)) @ D for c in (0, 1)]
+        pre = np.linalg.matrix_power(G[1] @ G[0], nu)
+        post = np.linalg.matrix_power(G[0] @ G[1], nu)
+        corr = np.zeros((m, m)) if l == 1 else P.toarray() @ dense(l + 1) @ R.toarray() @ D
+        return (np.eye(m) - post @ (np.eye(m) - corr) @ pre) @ np.linalg.inv(D)
+
+    ref = dense(0) @ b
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+    # and it differs from the full cycle
+    assert np.linalg.norm(vcycle(lev, tau, b, nu) - x) > 1e-6 * np.linalg.norm(x)
+
+
+def test_cycle_ending_on_the_finest_level_is_smoothing():
+    """Ending on level 0: nu red-black sweeps (colour 0, 1) then nu (colour 1,
+    0) from zero, written here as exact solves of the diagonal colour blocks."""
+    n, tau, nu = 12, 1e-2, 2
+    K = double_glazing(n, 0.005)[0]
+    lev = hierarchy(K, n, n, coarse_max=16)
+    b = np.random.default_rng(19).standard_normal(n * n)
+    x = vcycle(lev, tau, b, nu, coarse_ratio=1e12)
+    D = (sp.identity(n * n) + tau * K).tocsr()
+    col = colours(n, n)
+    y = np.zeros(n * n)
+    for c in [0, 1] * nu + [1, 0] * nu:
+        m = np.flatnonzero(col == c)
+        o = np.flatnonzero(col != c)
+        Dcc = D[m][:, m].toarray()
+        y[m] = np.linalg.solve(Dcc, b[m] - D[m][:, o] @ y[o])
+    assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y)
