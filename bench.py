@@ -265,7 +265,9 @@ def main():
         "dtype": "f64/f32",
         "data": "synthetic",
         "config": {"workload": "heat_2048x2048_gl7_ht1e-3_10steps", "n": n, "s": s, "h_t": h,
-                   "tableau": "gauss_legendre", "preconditioner": "P_LD, AMG V(2,2) red-black GS",
+                   "tableau": "gauss_legendre",
+                   "preconditioner": ("P_LD, AMG V(2,2) red-black GS, cycle ends at the first "
+                                      "level with tau max K_pp/S_pp <= 2"),
                    "fgmres_rtol": args.rtol, "u0": "8 random sine modes, seed 0",
                    "parallelism": "single GPU"},
         "roofline": roof,
