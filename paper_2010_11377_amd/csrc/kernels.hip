@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 
 #include "kernels.hpp"
 
@@ -447,15 +448,61 @@ __global__ void k_solve_upper(const double *__restrict__ H, int ldh, const doubl
   }
 }
 
-template <typename TZ>
+template <typename TZ, bool FIRST>
 __global__ void __launch_bounds__(kBlock)
     k_accumulate(const TZ *__restrict__ Z, size_t zs, const double *__restrict__ y, int k,
                  size_t n, double *__restrict__ acc) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n) return;
-  double a = acc[e];
+  double a = FIRST ? 0.0 : acc[e];
   for (int j = 0; j < k; ++j) a += y[j] * double(Z[(size_t)j * zs + e]);
   acc[e] = a;
+}
+
+// The same for four consecutive elements per thread (16-byte loads of Z and
+// acc): n and zs multiples of 4, Z and acc 16-byte aligned.
+template <typename TZ>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  __device__ static void load(const float *p, double (&v)[4]) {
+    const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  }
+};
+template <>
+struct Vec4<double> {
+  __device__ static void load(const double *p, double (&v)[4]) {
+    const double2 q0 = *reinterpret_cast<const double2 *>(p);
+    const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = q0.x;
+    v[1] = q0.y;
+    v[2] = q1.x;
+    v[3] = q1.y;
+  }
+};
+
+template <typename TZ, bool FIRST>
+__global__ void __launch_bounds__(kBlock)
+    k_accumulate4(const TZ *__restrict__ Z, size_t zs, const double *__restrict__ y, int k,
+                  size_t n4, double *__restrict__ acc) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n4) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!FIRST) Vec4<double>::load(acc + 4 * e, a);
+  for (int j = 0; j < k; ++j) {
+    double z[4];
+    Vec4<TZ>::load(Z + (size_t)j * zs + 4 * e, z);
+    const double yj = y[j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] += yj * z[q];
+  }
+  double2 *out = reinterpret_cast<double2 *>(acc + 4 * e);
+  out[0] = make_double2(a[0], a[1]);
+  out[1] = make_double2(a[2], a[3]);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -485,7 +532,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int r = 0; r < S; ++r) {
       const double b = rhs ? rhs[(size_t)r * N + p] : f[p];
       const double res = b - w[r];
-      V0[(size_t)r * N + p] = res;
+      if (V0) V0[(size_t)r * N + p] = res;
       val += res * res;
     }
   }
@@ -732,8 +779,20 @@ void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hi
 
 template <typename TZ>
 void accumulate_solution(const TZ *Z, size_t zs, const double *y, int k, size_t n, double *acc,
-                         hipStream_t st) {
-  k_accumulate<TZ><<<nblocks(n), kBlock, 0, st>>>(Z, zs, y, k, n, acc);
+                         bool first, hipStream_t st) {
+  const bool vec = n % 4 == 0 && zs % 4 == 0 && reinterpret_cast<uintptr_t>(Z) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(acc) % 16 == 0;
+  if (vec) {
+    const size_t n4 = n / 4;
+    if (first)
+      k_accumulate4<TZ, true><<<nblocks(n4), kBlock, 0, st>>>(Z, zs, y, k, n4, acc);
+    else
+      k_accumulate4<TZ, false><<<nblocks(n4), kBlock, 0, st>>>(Z, zs, y, k, n4, acc);
+  } else if (first) {
+    k_accumulate<TZ, true><<<nblocks(n), kBlock, 0, st>>>(Z, zs, y, k, n, acc);
+  } else {
+    k_accumulate<TZ, false><<<nblocks(n), kBlock, 0, st>>>(Z, zs, y, k, n, acc);
+  }
 }
 
 void combine_stages(const double *u_in, const double *x, const double *wts, int s, size_t N,
@@ -817,9 +876,9 @@ template void spmm_update<double>(const OpView<double> &, const OpView<double> *
                                   const double *, const KrylovState *, double *, double *,
                                   hipStream_t);
 template void accumulate_solution<float>(const float *, size_t, const double *, int, size_t,
-                                         double *, hipStream_t);
+                                         double *, bool, hipStream_t);
 template void accumulate_solution<double>(const double *, size_t, const double *, int, size_t,
-                                          double *, hipStream_t);
+                                          double *, bool, hipStream_t);
 
 }  // namespace kern
 }  // namespace irk

@@ -186,17 +186,19 @@ void givens(const double *h1, const double *h2, const double *partial_norm, int 
 // Back substitution H y = g for the leading k x k block, single block.
 void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);
 
-// acc (double, s*N) += sum_{j<k} y_j Z_j  (Z stride zs elements per column).
+// acc (double, s*N) += sum_{j<k} y_j Z_j  (Z stride zs elements per column);
+// first: acc = sum_{j<k} y_j Z_j (acc is not read).
 template <typename TZ>
 void accumulate_solution(const TZ *Z, size_t zs, const double *y, int k, size_t n, double *acc,
-                         hipStream_t st);
+                         bool first, hipStream_t st);
 
 // u_out = u_in + sum_i wts[i] * x_i   (x stage-major double, wts = h b).
 void combine_stages(const double *u_in, const double *x, const double *wts, int s, size_t N,
                     double *u_out, hipStream_t st);
 
-// r = rhs - (I (x) M + hA (x) K) x; V0 = r; partial norms.  rhs == nullptr
-// with f given means rhs = 1 (x) f; M == nullptr means M = I.
+// r = rhs - (I (x) M + hA (x) K) x; V0 = r (unless V0 == nullptr); partial
+// norms.  rhs == nullptr with f given means rhs = 1 (x) f; M == nullptr means
+// M = I.
 void residual_full(const OpView<double> &K, const OpView<double> *M, const double *x,
                    const double *hA, int s, const double *rhs, const double *f, double *V0,
                    double *partial, hipStream_t st);

@@ -760,8 +760,7 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
   const OpView<double> K = S->K64.view();
   T *Z = static_cast<T *>(S->Z);
 
-  HIP_TRY(hipMemsetAsync(S->acc, 0, sN * sizeof(double), st));
-  // initial residual = rhs (x0 = 0)
+  // initial residual = rhs (x0 = 0; the first cycle writes acc outright)
   if (sys.forward) {
     rhs_forward(K, sys.u, S->g, s, S->f, S->V, S->partial, st);
     finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
@@ -778,11 +777,12 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     stats->rel_resid_est = 0.0;
     stats->rel_resid_true = -1.0;
   }
-  if (!std::isfinite(beta0)) {
+  if (!std::isfinite(beta0) || beta0 == 0.0) {
+    HIP_TRY(hipMemsetAsync(S->acc, 0, sN * sizeof(double), st));
+    if (beta0 == 0.0) return IRK_OK;  // k = 0 solves the system exactly
     S->err = "non-finite right-hand side";
     return IRK_E_NONFINITE;
   }
-  if (beta0 == 0.0) return IRK_OK;  // k = 0 solves the system exactly
 
   double beta = beta0;
   int total = 0, restarts = 0;
@@ -853,15 +853,17 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     // x += Z y over the j columns of this cycle (a column that broke down is dropped)
     if (status == IRK_E_BREAKDOWN) --j;
     solve_upper(S->H, m + 1, S->gv, j, S->y, st);
-    accumulate_solution<T>(Z, sN, S->y, j, sN, S->acc, st);
+    accumulate_solution<T>(Z, sN, S->y, j, sN, S->acc, restarts == 0, st);
     if (status == IRK_E_BREAKDOWN || (stop && status == IRK_E_NOT_CONVERGED)) break;
     if (status == IRK_OK && !S->opt.true_resid) break;  // trust the estimate
     // true residual of the accumulated solution: verifies a converged estimate
     // (single-pass Gram-Schmidt can make the estimate optimistic) or starts
-    // the next restart cycle
-    residual_full(K, mass(S), S->acc, sys.hA, s, sys.forward ? nullptr : S->rhs, S->f, S->V,
-                  S->partial,
-                  st);
+    // the next restart cycle.  A converged estimate usually passes, so the
+    // residual vector itself is only stored when a next cycle needs it.
+    const double *rhs_full = sys.forward ? nullptr : S->rhs;
+    const bool need_v0 = status != IRK_OK;
+    residual_full(K, mass(S), S->acc, sys.hA, s, rhs_full, S->f, need_v0 ? S->V : nullptr,
+                  S->partial, st);
     finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
     HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -879,6 +881,10 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     if (total >= S->opt.max_iter) {
       status = IRK_E_NOT_CONVERGED;
       break;
+    }
+    if (!need_v0) {  // the estimate was optimistic: store the residual for the restart
+      residual_full(K, mass(S), S->acc, sys.hA, s, rhs_full, S->f, S->V, S->partial, st);
+      finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
     }
     status = IRK_E_NOT_CONVERGED;
     ++restarts;
@@ -988,7 +994,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     if (status == IRK_E_BREAKDOWN) --j;
     solve_upper(S->H, m + 1, S->gv, j, S->y, st);
     scale_by(S->y, S->scale, j, st);
-    accumulate_solution<double>(S->V, sN, S->y, j, sN, S->acc, st);
+    accumulate_solution<double>(S->V, sN, S->y, j, sN, S->acc, false, st);
     if (status == IRK_E_BREAKDOWN || (stop && status == IRK_E_NOT_CONVERGED)) break;
     if (status == IRK_OK && !S->opt.true_resid) break;
     // preconditioned residual of the accumulated solution: P^-1 (rhs - A k)
@@ -1346,15 +1352,14 @@ irk_status irk_apply_preconditioner(irk_solver *S, const double *v_dev, double *
     HIP_TRY(hipMemcpyAsync(S->scale, &one, sizeof(double), hipMemcpyHostToDevice, S->stream));
     HIP_TRY(hipMemcpyAsync(S->V, v_dev, S->sN * sizeof(double), hipMemcpyDeviceToDevice, S->stream));
     HIP_TRY(hipMemcpyAsync(S->y, &one, sizeof(double), hipMemcpyHostToDevice, S->stream));
-    HIP_TRY(hipMemsetAsync(z_dev, 0, S->sN * sizeof(double), S->stream));
     if (S->opt.precision == IRK_MIXED) {
       precondition<float>(S, S->V, S->scale, static_cast<float *>(S->Z), S->Cfwd, S->ord_fwd);
       irk::kern::accumulate_solution<float>(static_cast<float *>(S->Z), S->sN, S->y, 1, S->sN,
-                                            z_dev, S->stream);
+                                            z_dev, true, S->stream);
     } else {
       precondition<double>(S, S->V, S->scale, static_cast<double *>(S->Z), S->Cfwd, S->ord_fwd);
       irk::kern::accumulate_solution<double>(static_cast<double *>(S->Z), S->sN, S->y, 1, S->sN,
-                                             z_dev, S->stream);
+                                             z_dev, true, S->stream);
     }
     HIP_TRY(hipStreamSynchronize(S->stream));
     return IRK_OK;
