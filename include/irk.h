@@ -123,9 +123,12 @@ typedef struct {
   int graphs;      /* 1: each preconditioner application (s coupling passes
                       and V-cycles, a fixed kernel sequence per Krylov column)
                       is captured once into a HIP graph and replayed, which
-                      lowers the per-kernel launch cost; 0: direct launches.
-                      Both run the same kernels in the same order, so the
-                      results are identical. */
+                      lowers the host's per-kernel launch cost (small grids,
+                      where the host cannot keep ahead of the kernels); 0:
+                      direct launches (the default: on large grids the host
+                      keeps ahead anyway, and a graph launch delays its first
+                      kernel).  Both run the same kernels in the same order, so
+                      the results are identical. */
   double coarse_ratio; /* end of a block's V-cycle: the first level l whose
                       block S_l + tau_i K_l has tau_i max_p (K_l)_pp / (S_l)_pp
                       <= coarse_ratio (S_l, K_l the Galerkin mass and
@@ -146,7 +149,7 @@ typedef struct {
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
  * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR,
- * graphs 1, coarse_ratio 2. */
+ * graphs 0, coarse_ratio 2. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.

@@ -141,6 +141,7 @@ struct irk_solver {
   std::vector<PrecGraph> graphs;
   hipStream_t cap_stream = nullptr;  // capture only; replays go to `stream`
   long long graph_replays = 0;
+  hipEvent_t resid_ev = nullptr;  // recorded after an iteration's residual estimate reaches the host
 
   std::string err;
 };
@@ -181,7 +182,12 @@ void prof_end(irk_solver *S, const ProfTok &t) {
 
 // Resolve the recorded events; call only after the stream has synchronised.
 void prof_collect(irk_solver *S) {
+  std::vector<ProfTok> keep;
   for (const ProfTok &t : S->prof_pending) {
+    if (hipEventQuery(t.b) != hipSuccess) {  // still queued (work enqueued ahead)
+      keep.push_back(t);
+      continue;
+    }
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
     S->prof_ms += ms;
@@ -190,7 +196,7 @@ void prof_collect(irk_solver *S) {
     S->prof_pool.push_back(t.a);
     S->prof_pool.push_back(t.b);
   }
-  S->prof_pending.clear();
+  S->prof_pending.swap(keep);
 }
 
 // Coefficient bytes of one pass over a stored operator (0 for a constant one).
@@ -444,6 +450,7 @@ void alloc_workspace(irk_solver *S) {
   void *hp = nullptr;
   HIP_TRY(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault));
   S->host_resid = static_cast<double *>(hp);
+  HIP_TRY(hipEventCreateWithFlags(&S->resid_ev, hipEventDisableTiming));
 }
 
 template <typename T>
@@ -769,7 +776,11 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     finalize_norm(S->partial, nblk_full, S->scale, 0, S->norm_dev, st);
   }
   HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  // the first column's preconditioner depends only on the right-hand side:
+  // enqueued before the host reads ||rhs|| (unused if that is zero or not finite)
+  HIP_TRY(hipEventRecord(S->resid_ev, st));
+  precondition<T>(S, S->V, S->scale, Z, sys.C, sys.ord);
+  HIP_TRY(hipEventSynchronize(S->resid_ev));
   const double beta0 = S->host_resid[0];
   if (stats) {
     stats->iters = 0;
@@ -794,10 +805,13 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     HIP_TRY(hipMemcpyAsync(S->gv, &beta, sizeof(double), hipMemcpyHostToDevice, st));
     int j = 0;
     bool stop = false;
+    bool pre_next = restarts == 0;  // column j's preconditioner is already enqueued
+    double res_last = beta, rate = 0.5;
     for (; j < m; ++j) {
       const double *Vj = S->V + (size_t)j * sN;
       T *Zj = Z + (size_t)j * sN;
-      precondition<T>(S, Vj, S->scale + j, Zj, sys.C, sys.ord);
+      if (!pre_next) precondition<T>(S, Vj, S->scale + j, Zj, sys.C, sys.ord);
+      pre_next = false;
       const double kb = op_bytes(S, N, S->K64.npt, 8);
       const double zb = (double)sN * sizeof(T), vb = (double)sN * 8.0;
       ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb);
@@ -824,12 +838,30 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
              S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, st);
       HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
                              hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      // Column j+1's preconditioner needs V_{j+1} (written above), not the
+      // convergence decision.  When the estimate will almost surely stay above
+      // the tolerance (even at twice the last rate of decrease it would be 10x
+      // above), it is enqueued before the host waits for this estimate, so the
+      // GPU does not idle through the round trip; a misprediction leaves one
+      // unused column (results unchanged).
+      const bool spec = j + 1 < m && total + 1 < S->opt.max_iter &&
+                        res_last * rate * rate > 10.0 * S->opt.rtol * beta0;
+      if (spec) {
+        HIP_TRY(hipEventRecord(S->resid_ev, st));
+        precondition<T>(S, S->V + (size_t)(j + 1) * sN, S->scale + j + 1,
+                        Z + (size_t)(j + 1) * sN, sys.C, sys.ord);
+        pre_next = true;
+        HIP_TRY(hipEventSynchronize(S->resid_ev));
+      } else {
+        HIP_TRY(hipStreamSynchronize(st));
+      }
       prof_collect(S);
       ++total;
       const double res = S->host_resid[0];
       const int brk = (int)S->host_resid[1];
       est = res / beta0;
+      if (res > 0.0 && res_last > 0.0) rate = std::min(1.0, res / res_last);
+      res_last = res;
       if (brk == 1 || !std::isfinite(res)) {
         status = IRK_E_BREAKDOWN;
         S->err = "Krylov breakdown (non-finite or zero Hessenberg entry)";
@@ -1103,7 +1135,7 @@ void irk_default_options(irk_options *o) {
   o->rtol = 1e-8;
   o->side = IRK_RIGHT;
   o->interp = IRK_INTERP_LINEAR;
-  o->graphs = 1;
+  o->graphs = 0;
   o->coarse_ratio = 2.0;
 }
 
@@ -1376,6 +1408,7 @@ void irk_destroy(irk_solver *S) {
   for (hipEvent_t e : S->prof_pool) (void)hipEventDestroy(e);
   for (const auto &g : S->graphs) (void)hipGraphExecDestroy(g.exec);
   if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+  if (S->resid_ev) (void)hipEventDestroy(S->resid_ev);
   free_list(S->op_allocs);
   free_list(S->ws_allocs);
   if (S->host_resid) (void)hipHostFree(S->host_resid);

@@ -44,7 +44,7 @@ class IRKSolver:
 
     def __init__(self, A, b, c, K, h_t, grid, precision="fp64", precond="LD", restart=40,
                  max_iter=200, nu_pre=2, nu_post=2, coarse_max=64, rtol=1e-8, true_resid=True,
-                 reorth=0, side="right", M=None, interp="linear", graphs=True,
+                 reorth=0, side="right", M=None, interp="linear", graphs=None,
                  coarse_ratio=None, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("IRKSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -70,7 +70,8 @@ class IRKSolver:
         opt.reorth = int(reorth)
         opt.side = {"right": B.IRK_RIGHT, "left": B.IRK_LEFT}[side]
         opt.interp = {"linear": B.IRK_INTERP_LINEAR, "constant": B.IRK_INTERP_CONSTANT}[interp]
-        opt.graphs = 1 if graphs else 0
+        if graphs is not None:
+            opt.graphs = 1 if graphs else 0
         if coarse_ratio is not None:
             opt.coarse_ratio = float(coarse_ratio)
         self.options = opt

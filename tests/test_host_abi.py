@@ -44,7 +44,8 @@ def test_default_options():
     assert o.rtol == 1e-8
     assert o.side == B.IRK_RIGHT
     assert o.interp == B.IRK_INTERP_LINEAR
-    assert o.graphs == 1
+    assert o.graphs == 0
+    assert o.coarse_ratio == 2.0
 
 
 def test_status_strings():
