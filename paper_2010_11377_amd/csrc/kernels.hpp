@@ -10,6 +10,25 @@ namespace irk {
 constexpr int kBlock = 256;  // threads per block for point kernels (4 waves)
 constexpr int kMaxStages = 8;
 
+#ifdef __HIPCC__
+// Workgroups go to the eight XCDs (each with its own L2) in turn, so the
+// neighbouring tiles of a 2-D launch would sit on different XCDs and fetch
+// their shared halo rows and partial cache lines twice.  Tile of this
+// workgroup when each XCD takes a contiguous band of tiles (row-major over
+// the launch grid; the last total mod 8 workgroups keep their own tile).
+struct Tile2 {
+  int x, y;
+};
+__device__ __forceinline__ Tile2 xcd_tile() {
+  constexpr int kXcds = 8;
+  const int nx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int id = blockIdx.y * nx + blockIdx.x;
+  const int per = total / kXcds;
+  const int t = id < per * kXcds ? (id % kXcds) * per + id / kXcds : id;
+  return {t % nx, t / nx};
+}
+#endif
+
 // A stencil operator on one grid level, as seen by the kernels.
 //  cls != nullptr: constant-coefficient operator; cls[q * 9 + k] is
 //                  coefficient k of boundary class q (see node_class).

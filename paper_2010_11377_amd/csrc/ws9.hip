@@ -316,8 +316,9 @@ static_assert(kTY9 > ev9(2 * 3), "tile height must exceed the row halo for nu <=
 template <typename G>
 __device__ __forceinline__ bool place(const S9Op &o, Place &p) {
   const int wave = threadIdx.x >> 6;
-  p.OXn = blockIdx.x * G::TXO;
-  p.OYn = (blockIdx.y * kW9 + wave) * G::TY;
+  const Tile2 tile = xcd_tile();
+  p.OXn = tile.x * G::TXO;
+  p.OYn = (tile.y * kW9 + wave) * G::TY;
   if (p.OYn >= o.ny) return false;
   const int OX = min(p.OXn, o.nx - G::TXO), OY = p.OYn;
   p.X0 = OX - G::HX;

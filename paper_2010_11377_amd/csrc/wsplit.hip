@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(64 * kSW)
   using G = SGeomD<NU>;
   constexpr int H = G::H, TY = G::TY, R = G::R;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // Y0 uniform
-  const int OX = blockIdx.x * G::TXO, OY = (blockIdx.y * kSW + wave) * TY;
+  const Tile2 tile = xcd_tile();
+  const int OX = tile.x * G::TXO, OY = (tile.y * kSW + wave) * TY;
   if (OY >= o.ny) return;
   const int X0 = OX - H, Y0 = OY - H;
   STile<R> t;
@@ -333,7 +334,8 @@ __global__ void __launch_bounds__(64 * kSW)
   using G = SGeomU<NU>;
   constexpr int H = G::H, TY = G::TY, R = G::R;
   const int wave = threadIdx.x >> 6, lane = s_lane();
-  const int OX = blockIdx.x * G::TXO, OY = (blockIdx.y * kSW + wave) * TY;
+  const Tile2 tile = xcd_tile();
+  const int OX = tile.x * G::TXO, OY = (tile.y * kSW + wave) * TY;
   if (OY >= o.ny) return;
   const int X0 = OX - H, Y0 = OY - H;
   const int ncx = o.nx / 2, ncy = o.ny / 2;
@@ -406,7 +408,8 @@ __global__ void __launch_bounds__(64 * kSW)
     k_scouple(KOpD ko, const double *__restrict__ v, const double *__restrict__ scale_j,
               const float *__restrict__ z, CoupleList cl, int i, float *__restrict__ b) {
   const int wave = threadIdx.x >> 6, lane = s_lane();
-  const int OX = blockIdx.x * kCTXO, OY = (blockIdx.y * kSW + wave) * kCRows;
+  const Tile2 tile = xcd_tile();
+  const int OX = tile.x * kCTXO, OY = (tile.y * kSW + wave) * kCRows;
   if (OY >= ko.ny) return;
   const int X0 = OX - 2, gxa = X0 + 2 * lane;
   const size_t N = (size_t)ko.nx * ko.ny;
