@@ -185,7 +185,7 @@ __device__ __forceinline__ void tile_restrict(const OpView<T> &D, const T *cls_l
   const int ncx = D.nx / 2, ncy = D.ny / 2;
   for (int q = threadIdx.x; q < (TX / 2) * (TY / 2); q += NT) {
     const int qi = q % (TX / 2), qj = q / (TX / 2);
-    const int I = blockIdx.x * (TX / 2) + qi, J = blockIdx.y * (TY / 2) + qj;
+    const int I = (X0 + H) / 2 + qi, J = (Y0 + H) / 2 + qj;  // tile origin / 2
     if (I >= ncx || J >= ncy) continue;
     T acc = T(0);
 #pragma unroll
@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(kNT)
   __shared__ T sx[W * HH];
   __shared__ T scls[81];
   if (CLS) stage_cls(D.cls, scls);
-  const int X0 = blockIdx.x * TX - H, Y0 = blockIdx.y * TY - H;
+  const Tile2 tile = xcd_tile();
+  const int X0 = tile.x * TX - H, Y0 = tile.y * TY - H;
   tile_load<T, W, HH, kNT>(b, sb, X0, Y0, D.nx, D.ny);
   __syncthreads();
   T ci[9];
@@ -242,7 +243,8 @@ __global__ void __launch_bounds__(kNT)
     stage_cls(D.cls, scls);
     stage_cls(K.cls, sclk);
   }
-  const int X0 = blockIdx.x * TX - H, Y0 = blockIdx.y * TY - H;
+  const Tile2 tile = xcd_tile();
+  const int X0 = tile.x * TX - H, Y0 = tile.y * TY - H;
   const size_t N = (size_t)D.nx * D.ny;
   const double sc_j = *scale_j;
   bool any = false;
@@ -331,7 +333,8 @@ __global__ void __launch_bounds__(kNT)
   __shared__ T se[CW * CH];
   __shared__ T scls[81];
   if (CLS) stage_cls(D.cls, scls);
-  const int X0 = blockIdx.x * TX - H, Y0 = blockIdx.y * TY - H;
+  const Tile2 tile = xcd_tile();
+  const int X0 = tile.x * TX - H, Y0 = tile.y * TY - H;
   const int ncx = D.nx / 2, ncy = D.ny / 2;
   // coarse nodes that interpolate onto the fine region at margin m
   const int CX0 = ((X0 + m) >> 1) - 1, CY0 = ((Y0 + m) >> 1) - 1;

@@ -267,7 +267,8 @@ __global__ void __launch_bounds__(64 * kWaves)
   constexpr int R = TY + 2 * HY;
   constexpr int TXO = 64 - 2 * HX;
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int OX = blockIdx.x * TXO, OY = (blockIdx.y * kWaves + wave) * TY;
+  const Tile2 tile = xcd_tile();
+  const int OX = tile.x * TXO, OY = (tile.y * kWaves + wave) * TY;
   if (OY >= D.ny) return;  // whole wave leaves together
   const int X0 = OX - HX, Y0 = OY - HY;
   T b[R], x[R];
@@ -374,7 +375,8 @@ __global__ void __launch_bounds__(64 * kWaves)
   constexpr int CW = (64 - 2 * M) / 2 + 4, CH = (R - 2 * M) / 2 + 4;
   __shared__ T se_all[kWaves][CW * CH];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int OX = blockIdx.x * TXO, OY = (blockIdx.y * kWaves + wave) * TY;
+  const Tile2 tile = xcd_tile();
+  const int OX = tile.x * TXO, OY = (tile.y * kWaves + wave) * TY;
   const int X0 = OX - H, Y0 = OY - H;
   const int ncx = D.nx / 2, ncy = D.ny / 2;
   const int CX0 = ((X0 + M) >> 1) - 1, CY0 = ((Y0 + M) >> 1) - 1;
