@@ -147,10 +147,11 @@ void s9down(const OpView<float> &D, const float *classes, int nu, const float *b
 void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, const float *ec,
           const float *xpre, float *x, hipStream_t st);
 // b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K on an
-// nx x ny grid with even nx (FP32 z and b, FP64 arithmetic); k_interior is
-// a host copy of K's interior coefficients.
+// nx x ny grid with even nx (z and b float or double, FP64 arithmetic);
+// k_interior is a host copy of K's interior coefficients.
+template <typename T>
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
-             const float *z, const double *C, int s, int i, float *b, hipStream_t st);
+             const T *z, const double *C, int s, int i, T *b, hipStream_t st);
 // y[j] *= scale[j], j < k (left.hip).
 void scale_by(double *y, const double *scale, int k, hipStream_t st);
 // The FP32 tail with rows in registers (tail2.hip): levels of at most 64 x 64

@@ -632,13 +632,18 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
 }
 
 // The stage coupling as a streaming pass of its own (uniform five-point K,
-// FP32 z, FP64 arithmetic): b0 = scale_j v_i - K (sum_k C[k] z_k).
+// FP64 arithmetic): b0 = scale_j v_i - K (sum_k C[k] z_k).
 template <typename T>
 void couple_split(irk_solver *S, const double *v, const double *scale_j, const T *z,
                   const double *Crow, int i) {
-  if constexpr (std::is_same_v<T, float>)
-    irk::kern::scouple(S->nx, S->ny, S->K64.interior, v, scale_j, z, Crow, S->s, i,
-                       static_cast<float *>(S->b0), S->stream);
+  irk::kern::scouple<T>(S->nx, S->ny, S->K64.interior, v, scale_j, z, Crow, S->s, i,
+                        static_cast<T *>(S->b0), S->stream);
+}
+
+// K suits the streaming coupling pass: uniform five-point, even dimensions.
+bool kcouple_ok(const irk_solver *S) {
+  const OpView<double> k = S->K64.view();
+  return k.npt == 5 && k.uniform && k.cls && k.nx % 2 == 0 && k.ny % 2 == 0;
 }
 
 // z = P^-1 v by block substitution (Sec. 4.2).  v = V_j (lazy scale
@@ -659,13 +664,15 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
     bool ws9_0 = false;  // FP32 nine-point constant-coefficient finest level (M != I)
     if constexpr (std::is_same_v<T, float>)
       ws9_0 = D0 && !split_ok<T>(*D0) && ws9_usable(*D0, S->opt.nu_pre);
-    if (D0 && split_ok<T>(*D0) && split_ok<T>(Kdev<T>(S))) {
-      // streaming coupling pass, then the plain two-columns-per-lane V-cycle
+    const bool split64 = std::is_same_v<T, double> && D0 && kcouple_ok(S);
+    if ((D0 && split_ok<T>(*D0) && split_ok<T>(Kdev<T>(S))) || split64) {
+      // streaming coupling pass, then the plain V-cycle (FP32: two columns per
+      // lane on the finest level)
       ProfTok tk = prof_begin(S, IRK_KC_COUPLE, cbytes);
       couple_split<T>(S, v, scale_j, z, C + (size_t)i * S->s, i);
       prof_end(S, tk);
       vcycle<T>(S, i, b0, z + (size_t)i * N, false);
-    } else if (D0 && !ws9_0) {
+    } else if (D0 && !ws9_0 && !std::is_same_v<T, double>) {
       // coupling fused into the finest-level down pass (+ rc = R(b - D x))
       const DevOp<T> &D = *D0;
       ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,

@@ -367,10 +367,10 @@ __global__ void __launch_bounds__(64 * kSW)
 
 // Block-substitution coupling for stage i (Sec. 4.2) as a streaming pass:
 //   b = scale_j v_i - K c,   c = sum_k C[k] z_k,
-// K uniform five-point.  The arithmetic is FP64 (z is read as FP32) and only
-// b is rounded to FP32: for smooth stage vectors K c nearly cancels v_i, and
-// forming the difference in FP32 would leave FP32 noise of the size of v_i in
-// b, which costs the outer FGMRES iterations.  Each wave covers 124 output
+// K uniform five-point.  The arithmetic is FP64 (z may be FP32) and only b is
+// rounded to the V-cycle's precision: for smooth stage vectors K c nearly
+// cancels v_i, and forming the difference in FP32 would leave FP32 noise of
+// the size of v_i in b, which costs the outer FGMRES iterations.  Each wave covers 124 output
 // columns (two halo columns per side for the east/west couplings of c) and
 // kCRows rows, with c on kCRows + 2 rows in registers.  Every z, v and b
 // element is read or written about once: the pass streams.
@@ -403,10 +403,26 @@ __device__ __forceinline__ double s_prev_d(double v) {  // lane - 1 (0 in lane 0
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int NK>
+// Two adjacent elements of a float or double vector.
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+  using V = float2;
+  __device__ static V make(double a, double b) { return make_float2((float)a, (float)b); }
+};
+template <>
+struct Pair2<double> {
+  using V = double2;
+  __device__ static V make(double a, double b) { return make_double2(a, b); }
+};
+
+// T: the type of z and b (float for the FP32 V-cycles, double for the FP64 path).
+template <int NK, typename T>
 __global__ void __launch_bounds__(64 * kSW)
     k_scouple(KOpD ko, const double *__restrict__ v, const double *__restrict__ scale_j,
-              const float *__restrict__ z, CoupleList cl, int i, float *__restrict__ b) {
+              const T *__restrict__ z, CoupleList cl, int i, T *__restrict__ b) {
+  using P = Pair2<T>;
   const int wave = threadIdx.x >> 6, lane = s_lane();
   const Tile2 tile = xcd_tile();
   const int OX = tile.x * kCTXO, OY = (tile.y * kSW + wave) * kCRows;
@@ -425,7 +441,7 @@ __global__ void __launch_bounds__(64 * kSW)
       const size_t p = (size_t)gy * ko.nx + gxa;
 #pragma unroll
       for (int m = 0; m < NK; ++m) {
-        const float2 zz = *reinterpret_cast<const float2 *>(z + (size_t)cl.k[m] * N + p);
+        const typename P::V zz = *reinterpret_cast<const typename P::V *>(z + (size_t)cl.k[m] * N + p);
         ax += cl.c[m] * (double)zz.x;
         ay += cl.c[m] * (double)zz.y;
       }
@@ -446,8 +462,7 @@ __global__ void __launch_bounds__(64 * kSW)
       vb -= ko.c * cb[r + 1] + ko.s * cb[r] + ko.n * cb[r + 2] + ko.w * ca[r + 1] +
             ko.e * s_next_d(ca[r + 1]);
     }
-    if (out) *reinterpret_cast<float2 *>(b + (size_t)gy * ko.nx + gxa) =
-        make_float2((float)va, (float)vb);
+    if (out) *reinterpret_cast<typename P::V *>(b + (size_t)gy * ko.nx + gxa) = P::make(va, vb);
   }
 }
 
@@ -465,11 +480,12 @@ void sup_nu(const SOp &o, const float *b, const float *ec, float *x, hipStream_t
   k_sup<NU><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
 }
 
-void scouple_launch(const KOpD &ko, const double *v, const double *scale_j, const float *z,
-                    const CoupleList &cl, int nk, int i, float *b, hipStream_t st) {
+template <typename T>
+void scouple_launch(const KOpD &ko, const double *v, const double *scale_j, const T *z,
+                    const CoupleList &cl, int nk, int i, T *b, hipStream_t st) {
   const dim3 grid((ko.nx + kCTXO - 1) / kCTXO, (ko.ny + kCRows * kSW - 1) / (kCRows * kSW));
 #define L_SCOUPLE(NK_) \
-  k_scouple<NK_><<<grid, 64 * kSW, 0, st>>>(ko, v, scale_j, z, cl, i, b)
+  k_scouple<NK_, T><<<grid, 64 * kSW, 0, st>>>(ko, v, scale_j, z, cl, i, b)
   switch (nk) {
     case 0: L_SCOUPLE(0); break;
     case 1: L_SCOUPLE(1); break;
@@ -503,8 +519,9 @@ void sdown(const OpView<float> &D, const float *interior, int nu, const float *b
   IRK_S_NU(sdown_nu, make_sop(D, interior), b, rc, st);
 }
 
+template <typename T>
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
-             const float *z, const double *C, int s, int i, float *b, hipStream_t st) {
+             const T *z, const double *C, int s, int i, T *b, hipStream_t st) {
   CoupleList cl{};
   int nk = 0;
   for (int k = 0; k < s; ++k)
@@ -514,8 +531,12 @@ void scouple(int nx, int ny, const double *k_interior, const double *v, const do
       ++nk;
     }
   const KOpD ko{nx, ny, k_interior[1], k_interior[3], k_interior[4], k_interior[5], k_interior[7]};
-  scouple_launch(ko, v, scale_j, z, cl, nk, i, b, st);
+  scouple_launch<T>(ko, v, scale_j, z, cl, nk, i, b, st);
 }
+template void scouple<float>(int, int, const double *, const double *, const double *,
+                             const float *, const double *, int, int, float *, hipStream_t);
+template void scouple<double>(int, int, const double *, const double *, const double *,
+                              const double *, const double *, int, int, double *, hipStream_t);
 
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st) {
