@@ -94,6 +94,7 @@ class IRKSolver:
             raise B.IRKError(st, self.lib.irk_last_error(None).decode())
         self._h = handle
         self.last_stats = None
+        self.last_status = None
         self._source = None
 
     # -- lifecycle -----------------------------------------------------------
@@ -148,6 +149,7 @@ class IRKSolver:
         st = self.lib.irk_step(self._h, _dev(u, self.N, "u"), _dev(out, self.N, "out"),
                                ctypes.byref(stats))
         self.last_stats = stats
+        self.last_status = st
         self._check(st, allow_not_converged)
         return out
 
