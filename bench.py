@@ -39,9 +39,9 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # taken on: reported as null once that file changes.
 SPMM_UPDATE_TRAFFIC = {
     "source": os.path.join("paper_2010_11377_amd", "csrc", "kernels.hip"),
-    "sha256": "7fb694f28afc1303dd9a9e46610a58d2e5b42b84f56266fac5a709a4ab811f68",
-    "fetch_kib": (1.9999 * 58545.4, 1.9999 * 121244.9),  # a + b (j + 1), scaled
-    "write_kib": 229950.7,
+    "sha256": "d26324ca935cc82489df2b5e8610cc5c8e17995834f1a1148450960a428d1a1d",
+    "fetch_kib": (1.9999 * 58575.3, 1.9999 * 121244.5),  # a + b (j + 1), scaled
+    "write_kib": 229951.0,
 }
 
 

@@ -394,6 +394,9 @@ __global__ void __launch_bounds__(kRed)
 // Hessenberg column j: H[:, j] = h1 (+ h2), H[j+1, j] = ||v_{j+1}||, rotate
 // with the stored Givens rotations, form the new one, update g and the
 // residual estimate |g_{j+1}|, set the lazy scale of V_{j+1}, advance j.
+// FIRST_ONLY: no second Gram-Schmidt pass exists, partial_norm holds the
+// first pass's partial sums of ||v_{j+1}||^2 and h2 is not read.
+template <bool FIRST_ONLY>
 __global__ void __launch_bounds__(kRed)
     k_givens(const double *__restrict__ h1, const double *__restrict__ h2,
              const double *__restrict__ partial_norm, int nblk,
@@ -401,10 +404,11 @@ __global__ void __launch_bounds__(kRed)
              double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
              double *__restrict__ scale, KrylovState *__restrict__ ks, double beta, double rtol,
              double *__restrict__ host_resid) {
-  const bool second = !ks->skip_reorth;
-  const double nrm2s = second ? sum_partials(partial_norm, nblk) : 0.0;  // uniform branch
+  const bool second = !FIRST_ONLY && !ks->skip_reorth;
+  const bool sum = FIRST_ONLY || second;
+  const double nrm2s = sum ? sum_partials(partial_norm, nblk) : 0.0;  // uniform branch
   if (threadIdx.x != 0) return;
-  const double nrm2 = second ? nrm2s : norm_sq_first[0];
+  const double nrm2 = sum ? nrm2s : norm_sq_first[0];
   const int j = ks->j;
   double *Hc = H + (size_t)j * ldh;
   for (int m = 0; m <= j; ++m) Hc[m] = h1[m] + (second ? h2[m] : 0.0);
@@ -768,9 +772,13 @@ void reorth_decide(const double *partial_norm, int nblk, const double *h1, Krylo
 void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
             const double *norm_sq_first, double *H, int ldh, double *cs, double *sn, double *g,
             double *scale, KrylovState *ks, double beta, double rtol, double *host_resid,
-            hipStream_t st) {
-  k_givens<<<1, kRed, 0, st>>>(h1, h2, partial_norm, nblk, norm_sq_first, H, ldh, cs, sn, g,
-                                 scale, ks, beta, rtol, host_resid);
+            bool first_only, hipStream_t st) {
+  if (first_only)
+    k_givens<true><<<1, kRed, 0, st>>>(h1, h2, partial_norm, nblk, norm_sq_first, H, ldh, cs,
+                                       sn, g, scale, ks, beta, rtol, host_resid);
+  else
+    k_givens<false><<<1, kRed, 0, st>>>(h1, h2, partial_norm, nblk, norm_sq_first, H, ldh, cs,
+                                        sn, g, scale, ks, beta, rtol, host_resid);
 }
 
 void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st) {

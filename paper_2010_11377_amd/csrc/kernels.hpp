@@ -197,11 +197,13 @@ void reduce_cols(const double *partial, int nblk, const KrylovState *ks, int jma
 void reorth_decide(const double *partial_norm, int nblk, const double *h1, KrylovState *ks,
                    int mode, double *norm_sq, hipStream_t st);
 
-// Single-block Hessenberg/Givens step for column j (see solver).
+// Single-block Hessenberg/Givens step for column j (see solver).  With
+// first_only there is no second Gram-Schmidt pass: partial_norm/nblk are the
+// first pass's partial norms and neither h2 nor norm_sq_first is read.
 void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
             const double *norm_sq_first, double *H, int ldh, double *cs, double *sn, double *g,
             double *scale, KrylovState *ks, double beta, double rtol, double *host_resid,
-            hipStream_t st);
+            bool first_only, hipStream_t st);
 
 // Back substitution H y = g for the leading k x k block, single block.
 void solve_upper(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);

@@ -830,9 +830,11 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
                      st);
       prof_end(S, t2);
       // second classical Gram-Schmidt pass, skipped on the device when the
-      // first one kept most of ||w|| (reorth = 2) or never run (reorth = 0)
-      reorth_decide(S->pnorm, nblk_pt, S->h1, S->ks, S->opt.reorth, S->norm_dev + 1, st);
-      if (S->opt.reorth != 0) {
+      // first one kept most of ||w|| (reorth = 2) or never run (reorth = 0:
+      // then the Givens step sums the first pass's norm itself)
+      const bool first_only = S->opt.reorth == 0;
+      if (!first_only) {
+        reorth_decide(S->pnorm, nblk_pt, S->h1, S->ks, S->opt.reorth, S->norm_dev + 1, st);
         ProfTok t3 = prof_begin(S, IRK_KC_VEC_DOTS, vb * (j + 2));
         vec_dots(nullptr, sN, S->V, S->scale, S->ks, j, S->partial, st);
         prof_end(S, t3);
@@ -841,8 +843,9 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
         vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm2, st);
         prof_end(S, t4);
       }
-      givens(S->h1, S->h2, S->pnorm2, nblk_vec, S->norm_dev + 1, S->H, m + 1, S->cs, S->sn,
-             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, st);
+      givens(S->h1, S->h2, first_only ? S->pnorm : S->pnorm2, first_only ? nblk_pt : nblk_vec,
+             S->norm_dev + 1, S->H, m + 1, S->cs, S->sn, S->gv, S->scale, S->ks, beta0,
+             S->opt.rtol, S->dev_resid, first_only, st);
       HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
                              hipMemcpyDeviceToHost, st));
       // Column j+1's preconditioner needs V_{j+1} (written above), not the
@@ -1002,7 +1005,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       reduce_cols(S->partial, nblk_vec, S->ks, j, 0, 1, S->h2, st);
       vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm2, st);
       givens(S->h1, S->h2, S->pnorm2, nblk_vec, S->norm_dev + 1, S->H, m + 1, S->cs, S->sn,
-             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, st);
+             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, false, st);
       HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
                              hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
