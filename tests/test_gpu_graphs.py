@@ -1,5 +1,5 @@
 """GPU tests of the preconditioner replayed from HIP graphs (option graphs = 1,
-the default) against direct launches (graphs = 0).
+opt-in) against direct launches (graphs = 0, the default).
 
 Both run the same kernels in the same order on the same data, so every
 result must be bit-identical.  Each test replays the captured graphs many
