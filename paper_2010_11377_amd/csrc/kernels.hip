@@ -396,6 +396,8 @@ __global__ void __launch_bounds__(kRed)
 // residual estimate |g_{j+1}|, set the lazy scale of V_{j+1}, advance j.
 // FIRST_ONLY: no second Gram-Schmidt pass exists, partial_norm holds the
 // first pass's partial sums of ||v_{j+1}||^2 and h2 is not read.
+static_assert(kMaxKrylov < kRed, "one lane per Krylov column in k_givens");
+
 template <bool FIRST_ONLY>
 __global__ void __launch_bounds__(kRed)
     k_givens(const double *__restrict__ h1, const double *__restrict__ h2,
@@ -404,22 +406,33 @@ __global__ void __launch_bounds__(kRed)
              double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
              double *__restrict__ scale, KrylovState *__restrict__ ks, double beta, double rtol,
              double *__restrict__ host_resid) {
+  // column inputs are loaded by all lanes at once into LDS, so the serial
+  // rotation chain below runs on LDS values instead of dependent global loads
+  __shared__ double hc[kMaxKrylov + 1], csl[kMaxKrylov], snl[kMaxKrylov];
   const bool second = !FIRST_ONLY && !ks->skip_reorth;
   const bool sum = FIRST_ONLY || second;
-  const double nrm2s = sum ? sum_partials(partial_norm, nblk) : 0.0;  // uniform branch
-  if (threadIdx.x != 0) return;
-  const double nrm2 = sum ? nrm2s : norm_sq_first[0];
-  const int j = ks->j;
-  double *Hc = H + (size_t)j * ldh;
-  for (int m = 0; m <= j; ++m) Hc[m] = h1[m] + (second ? h2[m] : 0.0);
-  const double nrm = sqrt(nrm2);
-  Hc[j + 1] = nrm;
-  for (int m = 0; m < j; ++m) {
-    const double a = Hc[m], bb = Hc[m + 1];
-    Hc[m] = cs[m] * a + sn[m] * bb;
-    Hc[m + 1] = -sn[m] * a + cs[m] * bb;
+  const int j = ks->j;  // j < kMaxKrylov <= kRed
+  const int t = threadIdx.x;
+  if (t <= j) {
+    hc[t] = h1[t] + (second ? h2[t] : 0.0);
+    if (t < j) {
+      csl[t] = cs[t];
+      snl[t] = sn[t];
+    }
   }
-  const double a = Hc[j], bb = Hc[j + 1];
+  const double nrm2s = sum ? sum_partials(partial_norm, nblk) : 0.0;  // uniform branch
+  __syncthreads();
+  if (t != 0) return;
+  const double nrm2 = sum ? nrm2s : norm_sq_first[0];
+  double *Hc = H + (size_t)j * ldh;
+  const double nrm = sqrt(nrm2);
+  double bb = nrm;  // H[j+1, j] before the rotations
+  for (int m = 0; m < j; ++m) {
+    const double a = hc[m], b1 = hc[m + 1];
+    Hc[m] = csl[m] * a + snl[m] * b1;
+    hc[m + 1] = -snl[m] * a + csl[m] * b1;
+  }
+  const double a = hc[j];
   const double r = hypot(a, bb);
   double c = 1.0, sv = 0.0;
   if (r > 0.0) {
@@ -430,8 +443,9 @@ __global__ void __launch_bounds__(kRed)
   sn[j] = sv;
   Hc[j] = r;
   Hc[j + 1] = 0.0;
-  g[j + 1] = -sv * g[j];
-  g[j] = c * g[j];
+  const double gj = g[j];
+  g[j + 1] = -sv * gj;
+  g[j] = c * gj;
   const double res = fabs(g[j + 1]);
   scale[j + 1] = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
   const bool bad = !isfinite(nrm) || !isfinite(res) || !(r > 0.0);

@@ -9,6 +9,7 @@ namespace irk {
 
 constexpr int kBlock = 256;  // threads per block for point kernels (4 waves)
 constexpr int kMaxStages = 8;
+constexpr int kMaxKrylov = 200;  // longest FGMRES restart cycle (Krylov columns)
 
 #ifdef __HIPCC__
 // Workgroups go to the eight XCDs (each with its own L2) in turn, so the
@@ -200,6 +201,8 @@ void reorth_decide(const double *partial_norm, int nblk, const double *h1, Krylo
 // Single-block Hessenberg/Givens step for column j (see solver).  With
 // first_only there is no second Gram-Schmidt pass: partial_norm/nblk are the
 // first pass's partial norms and neither h2 nor norm_sq_first is read.
+// host_resid receives {|g_{j+1}|, breakdown flag}: a device-accessible address
+// of coherent pinned host memory, read by the host after the kernel completes.
 void givens(const double *h1, const double *h2, const double *partial_norm, int nblk,
             const double *norm_sq_first, double *H, int ldh, double *cs, double *sn, double *g,
             double *scale, KrylovState *ks, double beta, double rtol, double *host_resid,

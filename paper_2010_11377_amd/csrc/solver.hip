@@ -109,8 +109,10 @@ struct irk_solver {
   double *partial = nullptr, *pnorm = nullptr, *pnorm2 = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr, *y = nullptr;
   double *scale = nullptr, *h1 = nullptr, *h2 = nullptr, *norm_dev = nullptr;
-  double *dev_resid = nullptr;
-  double *host_resid = nullptr;  // pinned
+  // coherent pinned host memory: {residual estimate, breakdown flag} written
+  // by the Givens kernel through host_resid_dev, read by the host after sync
+  double *host_resid = nullptr;
+  double *host_resid_dev = nullptr;
   void *Z = nullptr;             // m * sN elements of float or double
   void *b0 = nullptr;            // level-0 right-hand side, N elements
   // levels 1.. of b, x and the stored pre-smoothed x (level 0: b0, z and xp0)
@@ -433,7 +435,6 @@ void alloc_workspace(irk_solver *S) {
   S->h1 = dalloc<double>(L, m + 2);
   S->h2 = dalloc<double>(L, m + 2);
   S->norm_dev = dalloc<double>(L, 2);
-  S->dev_resid = dalloc<double>(L, 2);
   S->ks = dalloc<KrylovState>(L, 1);
   const size_t es = elem_size(S);
   S->b0 = dalloc<char>(L, N * es);
@@ -448,8 +449,11 @@ void alloc_workspace(irk_solver *S) {
   S->levp = dalloc<char>(L, (tot + 1) * es);
   S->xp0 = dalloc<char>(L, N * es);  // level 0 is not in the level buffers
   void *hp = nullptr;
-  HIP_TRY(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
   S->host_resid = static_cast<double *>(hp);
+  void *dp = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(&dp, hp, 0));
+  S->host_resid_dev = static_cast<double *>(dp);
   HIP_TRY(hipEventCreateWithFlags(&S->resid_ev, hipEventDisableTiming));
 }
 
@@ -845,9 +849,7 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       }
       givens(S->h1, S->h2, first_only ? S->pnorm : S->pnorm2, first_only ? nblk_pt : nblk_vec,
              S->norm_dev + 1, S->H, m + 1, S->cs, S->sn, S->gv, S->scale, S->ks, beta0,
-             S->opt.rtol, S->dev_resid, first_only, st);
-      HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
-                             hipMemcpyDeviceToHost, st));
+             S->opt.rtol, S->host_resid_dev, first_only, st);
       // Column j+1's preconditioner needs V_{j+1} (written above), not the
       // convergence decision.  When the estimate will almost surely stay above
       // the tolerance (even at twice the last rate of decrease it would be 10x
@@ -1005,9 +1007,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       reduce_cols(S->partial, nblk_vec, S->ks, j, 0, 1, S->h2, st);
       vec_update(nullptr, sN, S->V, S->scale, S->h2, S->ks, S->pnorm2, st);
       givens(S->h1, S->h2, S->pnorm2, nblk_vec, S->norm_dev + 1, S->H, m + 1, S->cs, S->sn,
-             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->dev_resid, false, st);
-      HIP_TRY(hipMemcpyAsync(S->host_resid, S->dev_resid, 2 * sizeof(double),
-                             hipMemcpyDeviceToHost, st));
+             S->gv, S->scale, S->ks, beta0, S->opt.rtol, S->host_resid_dev, false, st);
       HIP_TRY(hipStreamSynchronize(st));
       ++total;
       const double res = S->host_resid[0];
@@ -1087,7 +1087,7 @@ double now_s() {
 bool valid_options(const irk_options &o, std::string &err) {
   if (o.precision != IRK_FP64 && o.precision != IRK_MIXED) return err = "bad precision", false;
   if (o.precond < IRK_PREC_LD || o.precond > IRK_PREC_J) return err = "bad precond", false;
-  if (o.restart < 1 || o.restart > 200) return err = "restart must be in 1..200", false;
+  if (o.restart < 1 || o.restart > irk::kMaxKrylov) return err = "restart must be in 1..200", false;
   if (o.max_iter < 1) return err = "max_iter must be >= 1", false;
   if (o.nu_pre < 1 || o.nu_pre > 3 || o.nu_post != o.nu_pre)
     return err = "nu_pre = nu_post in 1..3 is required", false;
