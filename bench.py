@@ -39,9 +39,9 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # taken on: reported as null once that file changes.
 SPMM_UPDATE_TRAFFIC = {
     "source": os.path.join("paper_2010_11377_amd", "csrc", "kernels.hip"),
-    "sha256": "d26324ca935cc82489df2b5e8610cc5c8e17995834f1a1148450960a428d1a1d",
-    "fetch_kib": (1.9999 * 58575.3, 1.9999 * 121244.5),  # a + b (j + 1), scaled
-    "write_kib": 229951.0,
+    "sha256": "0a7a77cd9bbe16f4d641dba2d833683c862e479eb609eef97c4847254dfb9739",
+    "fetch_kib": (1.9999 * 58533.7, 1.9999 * 121253.6),  # a + b (j + 1), scaled
+    "write_kib": 229950.8,
 }
 
 
