@@ -241,11 +241,6 @@ __device__ __forceinline__ WOp<T> make_wop(const OpView<T> &D) {
   return o;
 }
 
-// Is the whole wave region strictly inside the grid (interior class only)?
-__device__ __forceinline__ bool region_interior(int X0, int Y0, int R, int nx, int ny) {
-  return X0 >= 1 && Y0 >= 1 && X0 + 63 <= nx - 2 && Y0 + R - 1 <= ny - 2;
-}
-
 // Geometry per (type, nu): halo and rows (registers hold 2 rows per value
 // array, so doubles get fewer rows).
 template <typename T, int NU>
