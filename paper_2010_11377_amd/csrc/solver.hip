@@ -953,7 +953,7 @@ irk_status gmres_left(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
   using namespace irk::kern;
   hipStream_t st = S->stream;
   const int s = S->s, m = S->opt.restart;
-  const size_t N = S->N, sN = S->sN;
+  const size_t sN = S->sN;
   const int nblk_vec = (int)((sN + irk::kBlock * 4 - 1) / (irk::kBlock * 4));
   const int nblk_full = (int)((sN + irk::kBlock - 1) / irk::kBlock);
   const OpView<double> K = S->K64.view();
