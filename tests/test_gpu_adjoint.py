@@ -6,7 +6,9 @@ u_t = div(kappa grad u), homogeneous Dirichlet, Radau IIA 3).
 * parity with the CPU oracle's adjoint gradient on a small grid;
 * central finite differences of J on 16 seeded directions at the 256^2,
   20-step configuration (J = 1/2 ||u_T - u_target||^2, u_target from kappa = 1,
-  kappa = exp(g) with g a Gaussian random field).
+  kappa = exp(g) with g a Gaussian random field);
+* an operator update (new kappa) leaves the solver bit-identical to a fresh
+  setup with that kappa.
 """
 import sys
 
@@ -123,3 +125,32 @@ def test_gradient_finite_differences_256(dev):
         worst = max(worst, best)
     assert worst <= 1e-6
     S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_update_operator_equals_fresh_setup(dev, precision):
+    """irk_update_operator (new kappa: stiffness and hierarchy rebuilt, buffers
+    kept) leaves the solver in the state a fresh setup with that kappa has:
+    forward and adjoint steps agree bit for bit."""
+    from paper_2010_11377_amd.solver import IRKSolver
+    say("case update operator %s" % precision)
+    n, h = 96, 2e-3
+    A, b, c = tableaux.tableau("radau_iia", 3)
+    k1 = np.exp(workloads.gaussian_random_field(n + 2, seed=3))
+    k2 = np.exp(workloads.gaussian_random_field(n + 2, seed=4))
+    S = IRKSolver(A, b, c, problems.kappa_diffusion(k1), h, (n, n), precision=precision,
+                  rtol=1e-11, device=dev)
+    F = IRKSolver(A, b, c, problems.kappa_diffusion(k2), h, (n, n), precision=precision,
+                  rtol=1e-11, device=dev)
+    rng = np.random.default_rng(5)
+    u = torch.tensor(rng.standard_normal(n * n), dtype=torch.float64, device=dev)
+    lam = torch.tensor(rng.standard_normal(n * n), dtype=torch.float64, device=dev)
+    S.step(u)  # runs with the first kappa before the update
+    S.update_operator(problems.kappa_diffusion(k2))
+    for _ in range(2):
+        assert torch.equal(S.step(u), F.step(u))
+        assert S.last_stats.iters == F.last_stats.iters
+        for x, y in zip(S.adjoint_step(u, lam), F.adjoint_step(u, lam)):
+            assert torch.equal(x, y)
+    S.close()
+    F.close()
