@@ -2,7 +2,8 @@
 cap: the step reaches the oracle's exact step through many restart cycles,
 with the next column's preconditioner enqueued ahead of the convergence check
 at every column but the last of a cycle; a capped solve reports that it did
-not converge and still returns its best iterate.
+not converge and still returns its best iterate; a step written over its own
+input equals the out-of-place step.
 """
 import sys
 
@@ -75,4 +76,24 @@ def test_iteration_cap(dev, precision):
     e0 = np.linalg.norm(u0.cpu().numpy() - ref)
     say("case iteration cap %s: error %.2e (no step %.2e)" % (precision, e1, e0))
     assert e1 < 0.1 * e0
+    S.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("restart", [40, 3])
+def test_in_place_step(dev, precision, restart):
+    """irk_step with u_{n+1} in the buffer of u_n (allowed by the interface)
+    returns exactly the out-of-place result, also through restart cycles."""
+    from paper_2010_11377_amd.solver import IRKSolver
+    n, h = 80, 2e-3
+    say("case in-place step restart %d %s" % (restart, precision))
+    A, b, c = tableaux.tableau("radau_iia", 3)
+    S = IRKSolver(A, b, c, problems.heat(n), h, (n, n), precision=precision, restart=restart,
+                  max_iter=600, rtol=1e-10, device=dev)
+    u = torch.tensor(workloads.fourier_modes(n, seed=2), dtype=torch.float64, device=dev)
+    v = u.clone()
+    for _ in range(3):
+        u = S.step(u)
+        S.step(v, out=v)
+        assert torch.equal(u, v)
     S.close()
