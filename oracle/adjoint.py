@@ -21,13 +21,15 @@ Test infrastructure only (see the package docstring).
 """
 import numpy as np
 
-from .operators import kappa_diffusion_K
+from .operators import face_diffusion_K, kappa_diffusion_K
 from .step import DirectStepper
 
 
-def forward(A, b, kappa_nodes, h, u0, nsteps, length=1.0):
-    """Run the exact stepper; returns (u_N, list of (u_n, U_n) per step)."""
-    K = kappa_diffusion_K(kappa_nodes, length)
+def forward(A, b, kappa_nodes, h, u0, nsteps, length=1.0, K=None):
+    """Run the exact stepper; returns (u_N, list of (u_n, U_n) per step).
+    ``K`` given: use it instead of the operator of ``kappa_nodes``."""
+    if K is None:
+        K = kappa_diffusion_K(kappa_nodes, length)
     st = DirectStepper(A, b, K, h)
     A = np.asarray(A, dtype=np.float64)
     u = np.array(u0, dtype=np.float64)
@@ -46,9 +48,18 @@ def objective(A, b, kappa_nodes, h, u0, nsteps, u_target, length=1.0):
     return 0.5 * float(r @ r)
 
 
-def gradient(A, b, kappa_nodes, h, u0, nsteps, u_target, length=1.0):
+def objective_faces(A, b, kx, ky, h, u0, nsteps, u_target, length=1.0):
+    """J for an operator given by its face coefficients (``face_diffusion_K``)."""
+    uN, _, _ = forward(A, b, None, h, u0, nsteps, length, K=face_diffusion_K(kx, ky, length))
+    r = uN - u_target
+    return 0.5 * float(r @ r)
+
+
+def gradient(A, b, kappa_nodes, h, u0, nsteps, u_target, length=1.0, faces=False):
     """``(J, dJ/dkappa_nodes)``, the gradient with the shape of kappa_nodes
-    ((n+2) x (n+2))."""
+    ((n+2) x (n+2)).  ``faces=True`` returns ``(J, g, gx, gy)`` with the face
+    gradients ``gx`` (n, n+1) and ``gy`` (n+1, n) laid out as the face
+    coefficients of ``kappa_face_values``."""
     kn = np.asarray(kappa_nodes, dtype=np.float64)
     n = kn.shape[0] - 2
     hx = length / (n + 1)
@@ -80,4 +91,6 @@ def gradient(A, b, kappa_nodes, h, u0, nsteps, u_target, length=1.0):
     g[1:-1, 1:] += 0.5 * gx
     g[:-1, 1:-1] += 0.5 * gy
     g[1:, 1:-1] += 0.5 * gy
+    if faces:
+        return J, g, gx, gy
     return J, g

@@ -125,10 +125,17 @@ def kappa_diffusion_K(kappa_nodes, length=1.0):
     interior grid, ``u_Q = 0`` on the boundary (homogeneous Dirichlet).
     ``kappa_nodes`` has shape (n+2, n+2) (indexed [j, i]) including boundary
     nodes."""
-    kn = np.asarray(kappa_nodes, dtype=np.float64)
-    n = kn.shape[0] - 2
+    kx, ky = kappa_face_values(kappa_nodes)
+    return face_diffusion_K(kx, ky, length)
+
+
+def face_diffusion_K(kx, ky, length=1.0):
+    """The same operator from its face coefficients: ``kx`` (n, n+1) and ``ky``
+    (n+1, n) as returned by ``kappa_face_values``."""
+    kx = np.asarray(kx, dtype=np.float64)
+    ky = np.asarray(ky, dtype=np.float64)
+    n = kx.shape[0]
     h = length / (n + 1)
-    kx, ky = kappa_face_values(kn)
     N = n * n
     rows, cols, vals = [], [], []
     diag = np.zeros((n, n))

@@ -99,3 +99,43 @@ def test_adjoint_gradient_matches_finite_differences():
         assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
     # corner nodes touch no face
     assert grad[0, 0] == 0.0 and grad[-1, -1] == 0.0
+
+
+def test_face_gradient_matches_finite_differences():
+    """dJ/dkappa_f against central differences in random face directions
+    (the operator built from its face coefficients directly), and the nodal
+    gradient as the half-and-half chain of the face gradient."""
+    from oracle.operators import kappa_face_values
+    n, h, steps, s = 8, 2e-3, 3, 3
+    A, b, c = tableau("radau_iia", s)
+    kappa = np.exp(gaussian_random_field(n + 2, seed=3))
+    u0 = fourier_modes(n, seed=2)
+    u_target = adjoint.forward(A, b, np.ones((n + 2, n + 2)), h, u0, steps)[0]
+    J, g, gx, gy = adjoint.gradient(A, b, kappa, h, u0, steps, u_target, faces=True)
+    kx, ky = kappa_face_values(kappa)
+    assert abs(adjoint.objective_faces(A, b, kx, ky, h, u0, steps, u_target) - J) <= 1e-14 * J
+    rng = np.random.default_rng(17)
+    for _ in range(3):
+        dx, dy = rng.standard_normal(kx.shape), rng.standard_normal(ky.shape)
+        eps = 1e-4
+        Jp = adjoint.objective_faces(A, b, kx * np.exp(eps * dx), ky * np.exp(eps * dy), h, u0,
+                                     steps, u_target)
+        Jm = adjoint.objective_faces(A, b, kx * np.exp(-eps * dx), ky * np.exp(-eps * dy), h, u0,
+                                     steps, u_target)
+        fd = (Jp - Jm) / (2 * eps)
+        an = float(np.sum(gx * kx * dx) + np.sum(gy * ky * dy))
+        assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    # a single face: the east face of interior node (2, 3)
+    e = np.zeros_like(kx)
+    e[3, 3] = 1.0
+    eps = 1e-5
+    fd = (adjoint.objective_faces(A, b, kx + eps * e, ky, h, u0, steps, u_target)
+          - adjoint.objective_faces(A, b, kx - eps * e, ky, h, u0, steps, u_target)) / (2 * eps)
+    assert abs(fd - gx[3, 3]) <= 1e-6 * abs(gx[3, 3])
+    # nodal = each face's gradient split equally between its two nodes
+    chain = np.zeros_like(g)
+    chain[1:-1, :-1] += 0.5 * gx
+    chain[1:-1, 1:] += 0.5 * gx
+    chain[:-1, 1:-1] += 0.5 * gy
+    chain[1:, 1:-1] += 0.5 * gy
+    assert np.allclose(chain, g, rtol=0, atol=1e-15 * np.abs(g).max())

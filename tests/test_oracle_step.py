@@ -51,6 +51,9 @@ def test_eigen_matches_direct_double_glazing():
     a = run_steps(DirectStepper(A, b, K, h, g), u0, 4)
     e = run_steps(EigenStepper(A, b, K, h, g), u0, 4)
     assert np.linalg.norm(a - e) <= 1e-12 * np.linalg.norm(a)
+    # the other fill-reducing ordering and threaded factorisation: same solve
+    m = run_steps(EigenStepper(A, b, K, h, g, permc_spec="MMD_AT_PLUS_A", workers=3), u0, 4)
+    assert np.linalg.norm(a - m) <= 1e-12 * np.linalg.norm(a)
 
 
 def test_eigen_matches_direct_kappa():
