@@ -202,6 +202,24 @@ irk_status irk_step_stages(irk_solver *S, const double *u_n_dev, double *u_np1_d
 irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *lam_np1_dev,
                             double *lam_n_dev, double *psi_dev, double *U_dev, irk_stats *st);
 
+/* Gradient of J with respect to the face coefficients kappa_f of the
+ * diffusion operator (K u)_P = h_x^-2 sum_{faces (P,Q)} kappa_f (u_P - u_Q)
+ * (not in the paper; the derivative of the discrete stage system of Sec. 3.1
+ * with respect to a parameter of K, summed over the stages of one step):
+ * adds  dJ/dkappa_f = -h_x^-2 sum_i (psi_iP - psi_iQ)(U_iP - U_iQ)  for every
+ * face, boundary values of psi and U being zero.
+ * Layout of gface_dev (device, accumulated, not overwritten), full-grid node
+ * (I, J) with I in 0..nx+1, J in 0..ny+1 and interior node (i, j) = (I-1, J-1):
+ *   x faces first: ny rows of nx+1, entry J' * (nx+1) + I' is the face between
+ *     (I', J'+1) and (I'+1, J'+1);
+ *   then y faces:  ny+1 rows of nx, entry ny*(nx+1) + J' * nx + I' is the face
+ *     between (I'+1, J') and (I'+1, J'+1);
+ *   2 nx ny + nx + ny doubles in all.
+ * psi_dev, U_dev: device s*N doubles from irk_adjoint_step.  IRK_E_INVALID for
+ * a NULL pointer or h_x <= 0. */
+irk_status irk_grad_diffusion_faces(irk_solver *S, const double *psi_dev, const double *U_dev,
+                                    double h_x, double *gface_dev);
+
 /* Gradient of J with respect to nodal coefficients of the diffusion operator
  * (K u)_P = h_x^-2 sum_{faces (P,Q)} kappa_f (u_P - u_Q), kappa_f =
  * (kappa_P + kappa_Q)/2, on the (nx+2) x (ny+2) node grid including boundary

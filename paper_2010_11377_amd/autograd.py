@@ -8,6 +8,11 @@ reverse (``irk_adjoint_step``: the transposed stage system, preconditioned by
 the transposed block preconditioner) from the checkpointed ``u_n`` and
 accumulates ``dJ/dkappa`` on the GPU (``irk_grad_diffusion_nodes``).
 
+The solver is shared: another forward (a different kappa) may run between this
+forward and its backward.  The forward keeps its stiffness matrix and the
+solver's operator version; the backward reinstalls that matrix when the
+version has moved on, so the adjoint always uses the K of its own forward.
+
 The stiffness matrix is assembled on the host from ``kappa_nodes`` (problem
 set-up, like any CSR handed to ``irk_setup``); every solve, adjoint solve and
 the gradient accumulation run in the HIP library.
@@ -22,7 +27,9 @@ class IRKDiffusionFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, kappa_nodes, u0, solver, nsteps, h_x):
         kn = kappa_nodes.detach().to("cpu", torch.float64).numpy()
-        solver.update_operator(problems.kappa_diffusion(kn, length=h_x * (kn.shape[0] - 1)))
+        K = problems.kappa_diffusion(kn, length=h_x * (kn.shape[0] - 1))
+        ctx.op_version = solver.update_operator(K)
+        ctx.K = K
         u = u0.detach().contiguous()
         checkpoints = []
         for _ in range(nsteps):
@@ -38,6 +45,8 @@ class IRKDiffusionFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         solver = ctx.solver
+        if solver.op_version != ctx.op_version:
+            ctx.op_version = solver.update_operator(ctx.K)
         lam = grad_u.detach().to(torch.float64).contiguous()
         gnode = torch.zeros(ctx.kshape, dtype=torch.float64, device=lam.device)
         for u_n in reversed(ctx.saved_tensors):

@@ -83,6 +83,7 @@ _PROTOS = {
     "irk_step_stages": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(Stats)]),
     "irk_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Stats)]),
     "irk_grad_diffusion_nodes": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP]),
+    "irk_grad_diffusion_faces": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP]),
     "irk_apply_operator": (ctypes.c_int, [_VP, _VP, _VP]),
     "irk_apply_preconditioner": (ctypes.c_int, [_VP, _VP, _VP]),
     "irk_destroy": (None, [_VP]),

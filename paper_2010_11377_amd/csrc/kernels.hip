@@ -659,6 +659,40 @@ __global__ void __launch_bounds__(kBlock)
   gnode[P] += -0.5 * inv_h2 * acc;
 }
 
+// One thread per face.  x faces come first (ny rows of nx + 1), then y faces
+// (ny + 1 rows of nx); P is the face's node with the smaller full-grid index.
+__global__ void __launch_bounds__(kBlock)
+    k_grad_faces(const double *__restrict__ psi, const double *__restrict__ U, int s, int nx,
+                 int ny, double inv_h2, double *__restrict__ gface) {
+  const size_t nfx = (size_t)ny * (nx + 1), nfy = (size_t)(ny + 1) * nx;
+  const size_t f = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= nfx + nfy) return;
+  int PI, PJ, QI, QJ;
+  if (f < nfx) {
+    const int i = (int)(f % (nx + 1)), j = (int)(f / (nx + 1));
+    PI = i;
+    PJ = j + 1;
+    QI = i + 1;
+    QJ = j + 1;
+  } else {
+    const size_t g = f - nfx;
+    const int i = (int)(g % nx), j = (int)(g / nx);
+    PI = i + 1;
+    PJ = j;
+    QI = i + 1;
+    QJ = j + 1;
+  }
+  const size_t N = (size_t)nx * ny;
+  double acc = 0.0;
+  for (int st = 0; st < s; ++st) {
+    const double *ps = psi + (size_t)st * N;
+    const double *us = U + (size_t)st * N;
+    acc += (full_val(ps, PI, PJ, nx, ny) - full_val(ps, QI, QJ, nx, ny)) *
+           (full_val(us, PI, PJ, nx, ny) - full_val(us, QI, QJ, nx, ny));
+  }
+  gface[f] += -inv_h2 * acc;
+}
+
 __global__ void __launch_bounds__(kBlock)
     k_nonfinite(const double *__restrict__ x, size_t n, double *__restrict__ partial) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -872,6 +906,12 @@ void grad_nodes(const double *psi, const double *U, int s, int nx, int ny, doubl
                 double *gnode, hipStream_t st) {
   k_grad_nodes<<<nblocks((size_t)(nx + 2) * (ny + 2)), kBlock, 0, st>>>(psi, U, s, nx, ny, inv_h2,
                                                                          gnode);
+}
+
+void grad_faces(const double *psi, const double *U, int s, int nx, int ny, double inv_h2,
+                double *gface, hipStream_t st) {
+  const size_t nf = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
+  k_grad_faces<<<nblocks(nf), kBlock, 0, st>>>(psi, U, s, nx, ny, inv_h2, gface);
 }
 
 void nonfinite_check(const double *x, size_t n, double *partial, hipStream_t st) {

@@ -251,6 +251,14 @@ void scaled_broadcast(const double *lam, const double *wts, int s, size_t N, dou
 void grad_nodes(const double *psi, const double *U, int s, int nx, int ny, double inv_h2,
                 double *gnode, hipStream_t st);
 
+// Face gradient of the face-diffusion operator, accumulated into gface:
+// the x faces (ny rows of nx+1, face (i, j) between full-grid nodes (i, j+1)
+// and (i+1, j+1)) followed by the y faces (ny+1 rows of nx, face (i, j)
+// between (i+1, j) and (i+1, j+1)); each adds -h^-2 sum_i (psi_iP -
+// psi_iQ)(U_iP - U_iQ).
+void grad_faces(const double *psi, const double *U, int s, int nx, int ny, double inv_h2,
+                double *gface, hipStream_t st);
+
 // Count of non-finite entries (nonzero result = bad), via partial sums.
 void nonfinite_check(const double *x, size_t n, double *partial, hipStream_t st);
 

@@ -1377,6 +1377,17 @@ irk_status irk_grad_diffusion_nodes(irk_solver *S, const double *psi_dev, const 
   });
 }
 
+irk_status irk_grad_diffusion_faces(irk_solver *S, const double *psi_dev, const double *U_dev,
+                                    double h_x, double *gface_dev) {
+  if (!S || !psi_dev || !U_dev || !gface_dev || !(h_x > 0.0)) return IRK_E_INVALID;
+  return guarded(S, [&]() -> irk_status {
+    irk::kern::grad_faces(psi_dev, U_dev, S->s, S->nx, S->ny, 1.0 / (h_x * h_x), gface_dev,
+                          S->stream);
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return IRK_OK;
+  });
+}
+
 irk_status irk_apply_operator(irk_solver *S, const double *x_dev, double *y_dev) {
   if (!S || !x_dev || !y_dev) return IRK_E_INVALID;
   return guarded(S, [&]() -> irk_status {

@@ -96,6 +96,7 @@ class IRKSolver:
         self.last_stats = None
         self.last_status = None
         self._source = None
+        self.op_version = 0  # bumped by every update_operator
 
     # -- lifecycle -----------------------------------------------------------
     def close(self):
@@ -137,8 +138,12 @@ class IRKSolver:
         self._source = gt
 
     def update_operator(self, K):
+        """Replace K (same grid and structure); returns the new operator
+        version (``op_version``)."""
         csr, keep = _csr_struct(*K)
         self._check(self.lib.irk_update_operator(self._h, ctypes.byref(csr)))
+        self.op_version += 1
+        return self.op_version
 
     # -- steps -------------------------------------------------------------------
     def step(self, u, out=None, allow_not_converged=False):
@@ -184,6 +189,15 @@ class IRKSolver:
             self._h, _dev(psi.reshape(-1), self.s * self.N, "psi"),
             _dev(U.reshape(-1), self.s * self.N, "U"), float(h_x),
             _dev(gnode.reshape(-1), (self.nx + 2) * (self.ny + 2), "gnode")))
+
+    def grad_diffusion_faces(self, psi, U, h_x, gface):
+        """Accumulate dJ/dkappa_f into ``gface``: x faces (ny x (nx+1)) then
+        y faces ((ny+1) x nx), flattened."""
+        nf = self.ny * (self.nx + 1) + (self.ny + 1) * self.nx
+        self._check(self.lib.irk_grad_diffusion_faces(
+            self._h, _dev(psi.reshape(-1), self.s * self.N, "psi"),
+            _dev(U.reshape(-1), self.s * self.N, "U"), float(h_x),
+            _dev(gface.reshape(-1), nf, "gface")))
 
     def apply_operator(self, x):
         y = torch.empty_like(x)
