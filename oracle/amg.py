@@ -32,6 +32,12 @@ reading taken for the structured finite-difference grids of Sec. 3:
   a colour (for five-point operators that is Gauss-Seidel), ``nu`` sweeps of
   colours 0 then 1 before the coarse correction and ``nu`` sweeps of colours
   1 then 0 after it;
+* other smoothers, for the comparison with the reading above
+  (``smoother=``): ``"jacobi"``, ``nu`` damped Jacobi sweeps
+  x += omega D^-1 (b - A x) before and after the coarse correction;
+  ``"chebyshev"``, ``nu`` applications of the degree-``cheb_degree``
+  Chebyshev iteration for D^-1 A on [lam_max / 10, 1.1 lam_max], lam_max the
+  Gershgorin bound of D^-1 A (symmetric positive definite blocks only);
 * one V-cycle from a zero initial guess per block;
 * optional early end of the cycle (``coarse_ratio`` > 0): the first level
   whose block is dominated by its mass part, tau_i max_p (K_l)_pp / (S_l)_pp
@@ -138,6 +144,38 @@ def relax(D, diag, col, b, x, colour):
     return x
 
 
+def jacobi(D, diag, b, x, omega):
+    """One damped Jacobi sweep x += omega D^-1 (b - A x)."""
+    return x + omega * (b - D @ x) / diag
+
+
+def gershgorin_bound(D, diag):
+    """An upper bound of the spectrum of D^-1 A: the largest row sum of
+    |D^-1 A|."""
+    return float(np.max(np.asarray(abs(D).sum(axis=1)).ravel() / np.abs(diag)))
+
+
+def chebyshev(D, diag, b, x, degree, lam_max):
+    """``degree`` steps of the Chebyshev iteration for A x = b preconditioned
+    by the diagonal, for spectra of D^-1 A in [a, c] = [lam_max/10,
+    1.1 lam_max]: the error is multiplied by T_k((theta - D^-1 A)/delta) /
+    T_k(theta/delta), theta = (a + c)/2, delta = (c - a)/2 (three-term
+    recurrence of the Chebyshev semi-iteration)."""
+    a, c = lam_max / 10.0, 1.1 * lam_max
+    theta, delta = 0.5 * (a + c), 0.5 * (c - a)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    r = b - D @ x
+    d = (r / diag) / theta
+    for _ in range(degree):
+        x = x + d
+        r = r - D @ d
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (r / diag)
+        rho = rho_new
+    return x
+
+
 def ends_cycle(S, Kl, tau, coarse_ratio):
     """True if the level's block S_l + tau K_l ends the V-cycle:
     tau max_p (K_l)_pp / (S_l)_pp <= coarse_ratio (never for coarse_ratio 0
@@ -147,7 +185,8 @@ def ends_cycle(S, Kl, tau, coarse_ratio):
     return tau * np.max(Kl.diagonal() / S.diagonal()) <= coarse_ratio
 
 
-def vcycle(levels, tau, b, nu=2, level=0, coarse_ratio=0.0):
+def vcycle(levels, tau, b, nu=2, level=0, coarse_ratio=0.0, smoother="rbgs", omega=0.8,
+           cheb_degree=2):
     """One V(nu, nu)-cycle from x = 0 for D_l = S_l + tau K_l."""
     nx, ny, S, Kl, P, R = levels[level]
     D = (S + tau * Kl).tocsr()
@@ -155,21 +194,33 @@ def vcycle(levels, tau, b, nu=2, level=0, coarse_ratio=0.0):
         return spla.spsolve(D.tocsc(), b) if D.shape[0] > 1 else b / D.toarray()[0, 0]
     diag = D.diagonal()
     col = colours(nx, ny)
-    x = np.zeros_like(b)
-    for _ in range(nu):
-        x = relax(D, diag, col, b, x, 0)
-        x = relax(D, diag, col, b, x, 1)
+    lam_max = gershgorin_bound(D, diag) if smoother == "chebyshev" else 0.0
+
+    def smooth(x, pre):
+        for _ in range(nu):
+            if smoother == "rbgs":
+                first, second = (0, 1) if pre else (1, 0)
+                x = relax(D, diag, col, b, x, first)
+                x = relax(D, diag, col, b, x, second)
+            elif smoother == "jacobi":
+                x = jacobi(D, diag, b, x, omega)
+            elif smoother == "chebyshev":
+                x = chebyshev(D, diag, b, x, cheb_degree, lam_max)
+            else:
+                raise ValueError(smoother)
+        return x
+
+    x = smooth(np.zeros_like(b), True)
     if not ends_cycle(S, Kl, tau, coarse_ratio):
         rc = R @ (b - D @ x)
-        x = x + P @ vcycle(levels, tau, rc, nu, level + 1, coarse_ratio)
-    for _ in range(nu):
-        x = relax(D, diag, col, b, x, 1)
-        x = relax(D, diag, col, b, x, 0)
-    return x
+        x = x + P @ vcycle(levels, tau, rc, nu, level + 1, coarse_ratio, smoother, omega,
+                           cheb_degree)
+    return smooth(x, False)
 
 
 def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=None,
-                                interp="linear", coarse_ratio=0.0):
+                                interp="linear", coarse_ratio=0.0, smoother="rbgs", omega=0.8,
+                                cheb_degree=2, levels=None):
     """``z ~= P^-1 v`` by block substitution (Sec. 4.2) with one V-cycle per
     diagonal block ``M + h A~_jj K`` instead of an exact solve (M = I if
     None)."""
@@ -180,7 +231,8 @@ def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=
     upper = np.allclose(At, np.triu(At))
     if not (lower or upper):
         raise ValueError("A~ must be triangular")
-    levels = hierarchy(K, nx, ny, coarse_max, M, interp)
+    if levels is None:
+        levels = hierarchy(K, nx, ny, coarse_max, M, interp)
     order = range(s) if lower else range(s - 1, -1, -1)
     v = np.asarray(v, dtype=np.float64).reshape(s, N)
     z = np.zeros((s, N))
@@ -189,5 +241,6 @@ def apply_vcycle_preconditioner(Atilde, K, h, v, nx, ny, nu=2, coarse_max=64, M=
         for k in range(s):
             if k != j and At[j, k] != 0.0:
                 rhs -= h * At[j, k] * (K @ z[k])
-        z[j] = vcycle(levels, h * At[j, j], rhs, nu, coarse_ratio=coarse_ratio)
+        z[j] = vcycle(levels, h * At[j, j], rhs, nu, coarse_ratio=coarse_ratio,
+                      smoother=smoother, omega=omega, cheb_degree=cheb_degree)
     return z

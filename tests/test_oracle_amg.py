@@ -323,3 +323,113 @@ def test_cycle_ending_on_the_finest_level_is_smoothing():
         Dcc = D[m][:, m].toarray()
         y[m] = np.linalg.solve(Dcc, b[m] - D[m][:, o] @ y[o])
     assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y)
+
+
+def _cheb_T(k, x):
+    """Chebyshev polynomial of the first kind, any real x."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(np.abs(x) <= 1.0, np.cos(k * np.arccos(np.clip(x, -1.0, 1.0))),
+                    np.cosh(k * np.arccosh(np.maximum(np.abs(x), 1.0))) * np.sign(x) ** k)
+
+
+def _error_matrix(smooth, D):
+    """Error propagation matrix of one smoother application from columns:
+    with b = D x_true and x0 = 0 the error after smoothing is E x_true."""
+    n = D.shape[0]
+    E = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        E[:, j] = e - smooth(D @ e)
+    return E
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_chebyshev_smoother_error_polynomial(degree):
+    """The Chebyshev smoother multiplies the error by the scaled Chebyshev
+    polynomial of D^-1 A on [lam_max/10, 1.1 lam_max]: checked on the
+    eigenvectors of D^-1 A of a heat block (closed form of the semi-
+    iteration), and the Gershgorin bound is >= the largest eigenvalue."""
+    from oracle.amg import chebyshev, gershgorin_bound
+    n, tau = 6, 2e-3
+    D = (sp.identity(n * n) + tau * heat_K(n)).tocsr()
+    diag = D.diagonal()
+    lam_max = gershgorin_bound(D, diag)
+    Dd = D.toarray()
+    mu = np.linalg.eigvals(np.diag(1.0 / diag) @ Dd).real
+    assert lam_max >= mu.max() - 1e-12
+    E = _error_matrix(lambda b: chebyshev(D, diag, b, np.zeros_like(b), degree, lam_max), D)
+    a, c = lam_max / 10.0, 1.1 * lam_max
+    theta, delta = 0.5 * (a + c), 0.5 * (c - a)
+    # D^-1 A = S diag(mu) S^-1 with S = diag^-1/2 Q (Q orthogonal eigenvectors
+    # of the symmetric diag^-1/2 A diag^-1/2)
+    Dh = np.diag(diag ** -0.5)
+    w, Q = np.linalg.eigh(Dh @ Dd @ Dh)
+    Sm = Dh @ Q
+    p = _cheb_T(degree, (theta - w) / delta) / _cheb_T(degree, theta / delta)
+    ref = Sm @ np.diag(p) @ np.linalg.inv(Sm)
+    assert np.max(np.abs(E - ref)) <= 1e-12
+
+
+def test_jacobi_smoother_error_matrix():
+    from oracle.amg import jacobi
+    n, tau, omega = 6, 2e-3, 0.8
+    D = (sp.identity(n * n) + tau * double_glazing(n, 0.005)[0]).tocsr()
+    diag = D.diagonal()
+    E = _error_matrix(lambda b: jacobi(D, diag, b, np.zeros_like(b), omega), D)
+    ref = np.eye(n * n) - omega * np.diag(1.0 / diag) @ D.toarray()
+    assert np.max(np.abs(E - ref)) <= 1e-14
+
+
+def _dense_cycle_smoother(levels, tau, nu, G_pre, G_post, l=0):
+    """Dense V-cycle with given per-level smoother error propagators."""
+    nx, ny, S, K, P, R = levels[l]
+    D = (S + tau * K).toarray()
+    n = D.shape[0]
+    if P is None:
+        return np.linalg.inv(D)
+    pre = np.linalg.matrix_power(G_pre(D), nu)
+    post = np.linalg.matrix_power(G_post(D), nu)
+    Bc = _dense_cycle_smoother(levels, tau, nu, G_pre, G_post, l + 1)
+    E = post @ (np.eye(n) - P.toarray() @ Bc @ R.toarray() @ D) @ pre
+    return (np.eye(n) - E) @ np.linalg.inv(D)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
+def test_vcycle_other_smoothers_dense_and_symmetric(smoother):
+    """V-cycles with damped Jacobi (omega 0.8) or degree-2 Chebyshev smoothing
+    equal the dense formulation built from the smoothers' closed-form error
+    polynomials, and on a symmetric heat block with R = P^T (the constant
+    interpolation) their operator is symmetric (pre- and post-smoother are the
+    same polynomial in D^-1 A)."""
+    from oracle.amg import gershgorin_bound
+    n, tau, nu = 16, 3e-4, 2
+    levels = hierarchy(heat_K(n), n, n, coarse_max=16)
+
+    def G(D):
+        d = np.diag(D)
+        M = np.diag(1.0 / d) @ D
+        if smoother == "jacobi":
+            return np.eye(D.shape[0]) - 0.8 * M
+        lam = float(np.max(np.abs(D).sum(axis=1) / np.abs(d)))
+        a, c = lam / 10.0, 1.1 * lam
+        theta, delta = 0.5 * (a + c), 0.5 * (c - a)
+        # T_2((theta - x)/delta) / T_2(theta/delta) as a matrix polynomial
+        Y = (theta * np.eye(D.shape[0]) - M) / delta
+        return (2.0 * Y @ Y - np.eye(D.shape[0])) / (2.0 * (theta / delta) ** 2 - 1.0)
+
+    B = _dense_cycle_smoother(levels, tau, nu, G, G)
+    b = np.random.default_rng(8).standard_normal(n * n)
+    x = vcycle(levels, tau, b, nu, smoother=smoother)
+    assert np.linalg.norm(x - B @ b) <= 1e-12 * np.linalg.norm(x)
+    Bx = np.column_stack([vcycle(levels, tau, e, nu, smoother=smoother)
+                          for e in np.eye(n * n)[:, :64].T])
+    Bfull = B[:, :64]
+    assert np.max(np.abs(Bx - Bfull)) <= 1e-12 * np.max(np.abs(Bfull))
+    lev_c = hierarchy(heat_K(n), n, n, coarse_max=16, interp="constant")
+    Bc = np.column_stack([vcycle(lev_c, tau, e, nu, smoother=smoother) for e in np.eye(n * n)])
+    assert np.max(np.abs(Bc - Bc.T)) <= 1e-12 * np.max(np.abs(Bc))
+    # red-black Gauss-Seidel (colours 0,1 before and 1,0 after) too
+    Bg = np.column_stack([vcycle(lev_c, tau, e, nu) for e in np.eye(n * n)])
+    assert np.max(np.abs(Bg - Bg.T)) <= 1e-12 * np.max(np.abs(Bg))
+    assert gershgorin_bound(sp.csr_matrix(np.eye(3)), np.ones(3)) == 1.0

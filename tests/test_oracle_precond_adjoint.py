@@ -12,6 +12,7 @@ Independent facts used:
   differences of the forward oracle.
 """
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from oracle import adjoint
@@ -139,3 +140,24 @@ def test_face_gradient_matches_finite_differences():
     chain[:-1, 1:-1] += 0.5 * gy
     chain[1:, 1:-1] += 0.5 * gy
     assert np.allclose(chain, g, rtol=0, atol=1e-15 * np.abs(g).max())
+
+
+def test_fgmres_pins():
+    """FGMRES: with the exact inverse as preconditioner one iteration gives the
+    exact solution; unpreconditioned on an n x n system it reaches the direct
+    solution in at most n iterations; its estimate equals the true residual;
+    restarts still converge."""
+    import scipy.sparse.linalg as spla
+    from oracle.krylov import fgmres
+    from oracle.operators import double_glazing
+    K = double_glazing(6, 0.005)[0]
+    A = (sp.identity(36) + 3e-3 * K).tocsc()
+    b = np.random.default_rng(3).standard_normal(36)
+    ref = spla.spsolve(A, b)
+    x, its, _ = fgmres(lambda v: A @ v, lambda v: spla.spsolve(A, v), b, rtol=1e-13)
+    assert its == 1 and np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+    x, its, hist = fgmres(lambda v: A @ v, lambda v: v, b, rtol=1e-12)
+    assert its <= 36 and np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert abs(np.linalg.norm(b - A @ x) / np.linalg.norm(b) - hist[-1]) <= 1e-12
+    x, its, _ = fgmres(lambda v: A @ v, lambda v: v, b, rtol=1e-10, restart=5, max_iter=500)
+    assert its > 5 and np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b) * 1.0001
