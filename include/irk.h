@@ -191,6 +191,22 @@ irk_status irk_step(irk_solver *S, const double *u_n_dev, double *u_np1_dev, irk
 irk_status irk_step_stages(irk_solver *S, const double *u_n_dev, double *u_np1_dev,
                            double *k_dev, irk_stats *st);
 
+/* For callers that cannot allocate device memory at step time (HIP graph
+ * capture around the caller's own work, tight serving loops, harnesses that
+ * forbid hipMalloc): the same step as irk_step, with every buffer the step
+ * writes besides u_np1 (Krylov bases V and Z, right-hand sides, multigrid
+ * level vectors, reduction partials, Hessenberg and Givens data) taken from
+ * one static device array of 64 MiB per GPU instead of the solver's
+ * workspace.  Nothing is allocated or freed; the array is held by each GPU
+ * the library runs on until the process ends.  Results equal irk_step's.
+ * Needs (restart + 1) * 8 + restart * (4 or 8) + 16 bytes per stage unknown
+ * plus O(N) more; a solver whose step does not fit gets IRK_E_INVALID (the
+ * message states the size) and must use irk_step.  All solvers on one GPU
+ * share the array: calls that overlap on one GPU race.  Graph replay and
+ * kernel-class timing are not used during this call. */
+irk_status irk_step_noalloc(irk_solver *S, const double *u_n_dev, double *u_np1_dev,
+                            irk_stats *st);
+
 /* Discrete adjoint of irk_step (not in the paper): recomputes the forward
  * stages from the checkpoint u_n, solves the transposed stage system
  * (I + h A^T (x) K^T) psi = h (b (x) lam_np1) right-preconditioned by the

@@ -81,6 +81,7 @@ _PROTOS = {
     "irk_update_operator": (ctypes.c_int, [_VP, ctypes.POINTER(CSR)]),
     "irk_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(Stats)]),
     "irk_step_stages": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(Stats)]),
+    "irk_step_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(Stats)]),
     "irk_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Stats)]),
     "irk_grad_diffusion_nodes": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP]),
     "irk_grad_diffusion_faces": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP]),

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -71,6 +72,7 @@ struct HipError {
 
 struct irk_solver {
   hipStream_t stream = nullptr;
+  int device = 0;  // the HIP device current at setup
   int s = 0, nx = 0, ny = 0;
   size_t N = 0, sN = 0;
   double h = 0.0;
@@ -1125,6 +1127,124 @@ irk_status guarded(irk_solver *S, F &&fn) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free step (irk_step_noalloc).  One copy per
+// GPU, held from module load to process end.  Host code never uses the name
+// `scratch` as an address: each device's address comes from
+// hipGetSymbolAddress, taken once per device at setup with that device
+// current, and only that address reaches kernels and copies.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+bool g_scratch_done[kScratchDevices] = {};
+void *g_scratch_ptr[kScratchDevices] = {};
+hipError_t g_scratch_err[kScratchDevices] = {};
+
+// Record the device address of `scratch` on the current device (first call
+// per device only).  A failure is kept and reported by irk_step_noalloc.
+void init_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kScratchDevices || g_scratch_done[dev]) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_done[dev] = true;
+  g_scratch_err[dev] = e;
+  g_scratch_ptr[dev] = (e == hipSuccess) ? p : nullptr;
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(double *__restrict__ p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// The per-step buffers of a solver (everything a step writes besides its
+// output; the operators and the pinned host word stay the solver's).
+struct StepBuffers {
+  double *V, *acc, *rhs, *f, *zero, *partial, *pnorm, *pnorm2, *H, *cs, *sn, *gv, *y, *scale, *h1,
+      *h2, *norm_dev;
+  void *Z, *b0, *levb, *levx, *levp, *xp0;
+  KrylovState *ks;
+};
+
+StepBuffers get_buffers(const irk_solver *S) {
+  return StepBuffers{S->V,  S->acc, S->rhs,   S->f,     S->zero, S->partial, S->pnorm, S->pnorm2,
+                     S->H,  S->cs,  S->sn,    S->gv,    S->y,    S->scale,   S->h1,    S->h2,
+                     S->norm_dev, S->Z, S->b0, S->levb, S->levx, S->levp, S->xp0, S->ks};
+}
+
+void set_buffers(irk_solver *S, const StepBuffers &b) {
+  S->V = b.V;
+  S->acc = b.acc;
+  S->rhs = b.rhs;
+  S->f = b.f;
+  S->zero = b.zero;
+  S->partial = b.partial;
+  S->pnorm = b.pnorm;
+  S->pnorm2 = b.pnorm2;
+  S->H = b.H;
+  S->cs = b.cs;
+  S->sn = b.sn;
+  S->gv = b.gv;
+  S->y = b.y;
+  S->scale = b.scale;
+  S->h1 = b.h1;
+  S->h2 = b.h2;
+  S->norm_dev = b.norm_dev;
+  S->Z = b.Z;
+  S->b0 = b.b0;
+  S->levb = b.levb;
+  S->levx = b.levx;
+  S->levp = b.levp;
+  S->xp0 = b.xp0;
+  S->ks = b.ks;
+}
+
+// Lay the step buffers of S out from `base` (256-byte aligned pieces); with
+// base == nullptr only the size is computed.  `zero` has N elements here:
+// it only serves as the zero coarse correction (levels >= 1).
+size_t carve_buffers(const irk_solver *S, unsigned char *base, StepBuffers &b) {
+  const size_t m = (size_t)S->opt.restart, N = S->N, sN = S->sN, es = elem_size(S);
+  const size_t nblk_pt = (N + irk::kBlock - 1) / irk::kBlock;
+  const size_t nblk_vec = (sN + irk::kBlock * 4 - 1) / (irk::kBlock * 4);
+  const size_t nblk_full = (sN + irk::kBlock - 1) / irk::kBlock;
+  const size_t npn = std::max({nblk_pt, nblk_vec, nblk_full});
+  size_t tot = 0;
+  for (int l = 1; l < S->nlev; ++l) tot += (size_t)S->lnx[l] * S->lny[l];
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    void *p = base ? static_cast<void *>(base + off) : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  b.V = static_cast<double *>(take((m + 1) * sN * 8));
+  b.Z = take(m * sN * es);
+  b.acc = static_cast<double *>(take(sN * 8));
+  b.rhs = static_cast<double *>(take(sN * 8));
+  b.f = static_cast<double *>(take(N * 8));
+  b.zero = static_cast<double *>(take(N * 8));
+  b.partial = static_cast<double *>(take(S->partial_len * 8));
+  b.pnorm = static_cast<double *>(take(npn * 8));
+  b.pnorm2 = static_cast<double *>(take(npn * 8));
+  b.H = static_cast<double *>(take((m + 1) * m * 8));
+  b.cs = static_cast<double *>(take((m + 1) * 8));
+  b.sn = static_cast<double *>(take((m + 1) * 8));
+  b.gv = static_cast<double *>(take((m + 2) * 8));
+  b.y = static_cast<double *>(take((m + 1) * 8));
+  b.scale = static_cast<double *>(take((m + 2) * 8));
+  b.h1 = static_cast<double *>(take((m + 2) * 8));
+  b.h2 = static_cast<double *>(take((m + 2) * 8));
+  b.norm_dev = static_cast<double *>(take(2 * 8));
+  b.ks = static_cast<KrylovState *>(take(sizeof(KrylovState)));
+  b.b0 = take(N * es);
+  b.levb = take((tot + 1) * es);
+  b.levx = take((tot + 1) * es);
+  b.levp = take((tot + 1) * es);
+  b.xp0 = take(N * es);
+  return off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1245,6 +1365,9 @@ irk_status irk_setup(irk_solver **out, const irk_butcher *tab, const irk_csr *M,
     }
     irk_status r = build_operators(S, K);
     if (r != IRK_OK) return r;
+    // the device that holds the operators (and the workspace below)
+    HIP_TRY(hipGetDevice(&S->device));
+    init_scratch(S->device);
     alloc_workspace(S);
     return IRK_OK;
   });
@@ -1321,6 +1444,54 @@ irk_status irk_step_stages(irk_solver *S, const double *u_n_dev, double *u_np1_d
                            irk_stats *st) {
   if (!k_dev) return IRK_E_INVALID;
   return step_impl(S, u_n_dev, u_np1_dev, k_dev, st);
+}
+
+irk_status irk_step_noalloc(irk_solver *S, const double *u_n_dev, double *u_np1_dev,
+                            irk_stats *st) {
+  if (!S || !u_n_dev || !u_np1_dev) return IRK_E_INVALID;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (S->device < 0 || S->device >= kScratchDevices || !g_scratch_done[S->device]) {
+      S->err = "irk_step_noalloc: no static scratch address for this device";
+      return IRK_E_HIP;
+    }
+    if (!g_scratch_ptr[S->device]) {
+      S->err = std::string("irk_step_noalloc: hipGetSymbolAddress failed: ") +
+               hipGetErrorString(g_scratch_err[S->device]);
+      return IRK_E_HIP;
+    }
+    base = g_scratch_ptr[S->device];
+  }
+  StepBuffers mine{};
+  const size_t need = carve_buffers(S, nullptr, mine);
+  if (need > kScratchBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "irk_step_noalloc: this solver's step needs %zu bytes of scratch, more than the "
+                  "static %zu bytes (use irk_step)",
+                  need, kScratchBytes);
+    S->err = msg;
+    return IRK_E_INVALID;
+  }
+  carve_buffers(S, static_cast<unsigned char *>(base), mine);
+  // run the ordinary step on the static buffers: no graph capture (it would
+  // allocate), no event timing; the solver's own buffers come back afterwards
+  const StepBuffers own = get_buffers(S);
+  const int graphs = S->opt.graphs, prof = S->prof_sel;
+  set_buffers(S, mine);
+  S->opt.graphs = 0;
+  S->prof_sel = -1;
+  irk_status r = guarded(S, [&]() -> irk_status {
+    k_fill_zero<<<(unsigned)((S->N + 255) / 256), 256, 0, S->stream>>>(S->zero, S->N);
+    HIP_TRY(hipGetLastError());
+    return IRK_OK;
+  });
+  if (r == IRK_OK) r = step_impl(S, u_n_dev, u_np1_dev, nullptr, st);
+  set_buffers(S, own);
+  S->opt.graphs = graphs;
+  S->prof_sel = prof;
+  return r;
 }
 
 irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *lam_np1_dev,

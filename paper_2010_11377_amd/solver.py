@@ -158,6 +158,17 @@ class IRKSolver:
         self._check(st, allow_not_converged)
         return out
 
+    def step_noalloc(self, u, out):
+        """``irk_step_noalloc``: the step on the library's static scratch (no
+        device allocation in the call; ``out`` must be given)."""
+        stats = B.Stats()
+        st = self.lib.irk_step_noalloc(self._h, _dev(u, self.N, "u"), _dev(out, self.N, "out"),
+                                       ctypes.byref(stats))
+        self.last_stats = stats
+        self.last_status = st
+        self._check(st)
+        return out
+
     def step_stages(self, u):
         """One step that also returns the stage vectors k, shape (s, N)."""
         out = torch.empty_like(u)
