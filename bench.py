@@ -19,6 +19,13 @@ steps, giving its achieved bandwidth against the HBM peak.
 The CPU baseline is the oracle (exact sine-transform stepper) on the host,
 and its result also gives the relative L2 error of both GPU paths.
 
+A second workload is reported beside the headline (key "double_glazing"):
+the double-glazing advection-diffusion problem on a 1024 x 1024 grid
+(eps = 1/200, upwind differences, hot east wall, u0 = 0), 5-stage Radau IIA,
+h_t = 5e-3, 20 steps, FP32 V-cycles inside FP64 FGMRES at tolerance 1e-8, with
+its own dominant-kernel bandwidth and its error against the oracle's
+eigen-decoupled exact stepper (sparse LUs on the host, about a minute).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
@@ -84,6 +91,11 @@ def parse():
     ap.add_argument("--graphs", action="store_true",
                     help="replay the preconditioner from captured HIP graphs instead of "
                          "launching its kernels directly")
+    ap.add_argument("--no-double-glazing", action="store_true",
+                    help="skip the 1024^2 double-glazing workload")
+    ap.add_argument("--dg-steps", type=int, default=20)
+    ap.add_argument("--no-dg-oracle", action="store_true",
+                    help="skip the oracle check of the double-glazing run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling hardware byte counters)")
@@ -142,6 +154,63 @@ def class_shares(S, u0, steps, torch):
         p = S.profile_read()
         out[kc] = {"ms": p["ms"] / steps, "bytes": p["bytes"] / steps, "launches": p["launches"] / steps}
     S.profile_select(None)
+    return out
+
+
+def roofline_of(prof, dominant):
+    if not prof or prof["launches"] == 0 or prof["ms"] <= 0:
+        return None
+    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "kernel": dominant,
+            "launches": prof["launches"], "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 2),
+            "bytes_per_launch": round(prof["bytes"] / prof["launches"])}
+
+
+def double_glazing_run(args, torch, np, dev):
+    """The 1024^2 double-glazing workload: timed steps, kernel classes, the
+    dominant class's bandwidth and (optionally) the error against the oracle."""
+    from paper_2010_11377_amd import problems, tableaux
+    from paper_2010_11377_amd.solver import IRKSolver
+    n, s, h, eps, K = 1024, 5, 5e-3, 0.005, args.dg_steps
+    A, b, c = tableaux.tableau("radau_iia", s)
+    ip, ix, d, g = problems.double_glazing(n, eps)
+    t0 = time.perf_counter()
+    S = IRKSolver(A, b, c, (ip, ix, d), h, (n, n), precision="mixed", rtol=args.rtol,
+                  graphs=args.graphs, device=dev)
+    S.set_source(g)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    u0 = torch.zeros(n * n, dtype=torch.float64, device=dev)
+    shares = class_shares(S, u0, 1, torch) if args.profile_steps > 0 else None
+    dom = max(shares, key=lambda k: shares[k]["ms"]) if shares else None
+    u, secs, iters, prof = timed_run(S, u0, K, 1, torch, dom)
+    S.close()
+    log("[bench] double glazing 1024^2 RIIA5: %d steps in %.4fs, iters %s, dominant %s" % (
+        K, secs, iters, dom))
+    out = {"workload": "double_glazing_1024x1024_eps0.005_radau5_ht5e-3_%dsteps" % K,
+           "precision": "FP32 V-cycles in FP64 FGMRES", "fgmres_rtol": args.rtol,
+           "steps": K, "steps_per_s": round(K / secs, 3), "ms_per_step": round(1e3 * secs / K, 3),
+           "iters_per_step": iters, "setup_s": round(t_setup, 2),
+           "roofline": roofline_of(prof, dom)}
+    if shares:
+        out["kernel_classes"] = {k: {"ms_per_step": round(v["ms"], 3),
+                                     "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                                 for k, v in shares.items()}
+    if not args.no_dg_oracle and not args.no_cpu_baseline:
+        from oracle.operators import double_glazing
+        from oracle.step import EigenStepper
+        from oracle.tableau import tableau as oracle_tableau
+        Ko, go = double_glazing(n, eps)
+        Ao, bo, _ = oracle_tableau("radau_iia", s)
+        t0 = time.perf_counter()
+        st = EigenStepper(Ao, bo, Ko, h, go, permc_spec="MMD_AT_PLUS_A", workers=3)
+        ref = np.zeros(n * n)
+        for _ in range(K):
+            ref = st.step(ref)
+        out["rel_err_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
+        log("[bench] double glazing oracle %.1fs, rel err %.2e" % (time.perf_counter() - t0,
+                                                                  out["rel_err_vs_oracle"]))
     return out
 
 
@@ -266,7 +335,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64/f32",
         "data": "synthetic",
-        "config": {"workload": "heat_2048x2048_gl7_ht1e-3_10steps", "n": n, "s": s, "h_t": h,
+        "config": {"workload": "heat_2048x2048_gl7_ht1e-3_%dsteps" % K, "n": n, "s": s, "h_t": h,
                    "tableau": "gauss_legendre",
                    "preconditioner": ("P_LD, AMG V(2,2) red-black GS, cycle ends at the first "
                                       "level with tau max K_pp/S_pp <= 2"),
@@ -302,6 +371,8 @@ def main():
         # the many small V-cycle kernels this sum exceeds the uninstrumented step
         # (a rocprofv3 kernel trace sums to the step time)
         line["event_timed_class_ms_over_step_ms"] = round(tot_ms / (1e3 * head["secs"] / K), 3)
+    if not args.no_double_glazing:
+        line["double_glazing"] = double_glazing_run(args, torch, np, dev)
     print(json.dumps(line), flush=True)
 
 

@@ -1,4 +1,5 @@
-"""Build libirk.so (HIP, gfx950) in-tree, and the host-only test library.
+"""Build libirk.so (HIP, gfx950) in-tree, the host-only test library and its
+address/undefined-behaviour sanitizer build.
 
 ``python -m paper_2010_11377_amd.build`` or ``build()``.
 """
@@ -50,8 +51,14 @@ def build(verbose=False):
     out2 = _run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", host + ".tmp",
                  "host_setup.cpp", "host_test_api.cpp"])
     os.replace(host + ".tmp", host)
+    # the same host code under AddressSanitizer + UBSan (g++ only, no GPU code)
+    asan = os.path.join(HERE, "libirk_host_asan.so")
+    out3 = _run(["g++", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                 "-fno-sanitize-recover=undefined", "-std=c++17", "-fPIC", "-shared", "-o",
+                 asan + ".tmp", "host_setup.cpp", "host_test_api.cpp"])
+    os.replace(asan + ".tmp", asan)
     if verbose:
-        print(out, out2, sep="\n")
+        print(out, out2, out3, sep="\n")
     return lib
 
 

@@ -15,7 +15,8 @@ from paper_2010_11377_amd import binding as B
 from paper_2010_11377_amd import problems
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HOST_LIB = os.path.join(ROOT, "paper_2010_11377_amd", "libirk_host_test.so")
+HOST_LIB = os.environ.get("IRK_HOST_TEST_LIB") or os.path.join(ROOT, "paper_2010_11377_amd",
+                                                            "libirk_host_test.so")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(B.LIB_PATH),
                                 reason="libirk.so not built (run __graft_entry__.build())")
