@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 
 HIP_SOURCES = ["host_setup.cpp", "kernels.hip", "vcycle.hip", "wtile.hip", "wsplit.hip",
-               "ws9.hip", "tail2.hip", "left.hip", "solver.hip"]
+               "wfine.hip", "ws9.hip", "tail2.hip", "left.hip", "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -71,6 +71,21 @@ struct TailDesc {
   const T *CinvT;  // null: the coarsest level returns x = 0 (the cycle ends one level up)
 };
 
+// The finest level of the stage blocks D_i = I + tau_i K (M = I) for the
+// passes that keep the pre-smoothed x (wfine.hip): either K per node, packed
+// in the passes' precision (kq: S, W, E, N of node p at 4p..4p+3; kc: centre),
+// with tau_i per stage, or (kq == nullptr) a uniform constant-coefficient
+// five-point stencil per stage, cs[i] = (S, W, C, E, N) of D_i.
+template <typename T>
+struct FineOp {
+  int nx = 0, ny = 0;
+  T pw = T(0);  // prolongation weight of the outermost fine node
+  const T *kq = nullptr;
+  const T *kc = nullptr;
+  T tau[kMaxStages] = {};
+  T cs[kMaxStages][5] = {};
+};
+
 // Scalars the Krylov kernels read from device memory so that a whole
 // iteration can be replayed without host arguments changing.
 struct KrylovState {
@@ -153,6 +168,19 @@ void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, 
 template <typename T>
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
              const T *z, const double *C, int s, int i, T *b, hipStream_t st);
+// The same coupling with K stored per node (FP64 arrays, karr[k * N + p],
+// five-point), wfine.hip.
+template <typename T>
+void scouple_var(int nx, int ny, const double *karr, const double *v, const double *scale_j,
+                 const T *z, const double *C, int s, int i, T *b, hipStream_t st);
+// Finest-level down pass of stage block `stage`: pre-smoothing from x = 0,
+// rc = R (b - D x), and the pre-smoothed x of every node into xpre.  nx, ny
+// even.  Up pass: x = xpre + P ec, then the post-smoothing (wfine.hip).
+template <typename T>
+void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st);
+template <typename T>
+void fup(const FineOp<T> &F, int stage, int nu, const T *b, const T *xpre, const T *ec, T *x,
+         hipStream_t st);
 // y[j] *= scale[j], j < k (left.hip).
 void scale_by(double *y, const double *scale, int k, hipStream_t st);
 // The FP32 tail with rows in registers (tail2.hip): levels of at most 64 x 64
