@@ -152,16 +152,19 @@ void sdown(const OpView<float> &D, const float *interior, int nu, const float *b
            hipStream_t st);
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st);
-// FP32 nine-point constant-coefficient levels, two columns per lane
-// (ws9.hip); `classes` is a host copy of the 81 class coefficients.  The down
-// pass stores its pre-smoothed x in xpre (a level-sized buffer), which the up
-// pass starts from.  ws9_ok tells whether the level's grid shape fits the
-// tiling (both passes must run these kernels).
-bool ws9_ok(const OpView<float> &D, int nu);
-void s9down(const OpView<float> &D, const float *classes, int nu, const float *b, float *rc,
-            float *xpre, hipStream_t st);
-void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, const float *ec,
-          const float *xpre, float *x, hipStream_t st);
+// Nine-point constant-coefficient levels, two columns per lane, FP32 or
+// FP64 (ws9.hip); `classes` is a host copy of the 81 class coefficients.
+// The down pass stores its pre-smoothed x in xpre (a level-sized buffer),
+// which the up pass starts from.  ws9_ok tells whether the level's grid
+// shape fits the tiling (both passes must run these kernels).
+template <typename T>
+bool ws9_ok(const OpView<T> &D, int nu);
+template <typename T>
+void s9down(const OpView<T> &D, const T *classes, int nu, const T *b, T *rc, T *xpre,
+            hipStream_t st);
+template <typename T>
+void s9up(const OpView<T> &D, const T *classes, int nu, const T *b, const T *ec, const T *xpre,
+          T *x, hipStream_t st);
 // b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K on an
 // nx x ny grid with even nx (z and b float or double, FP64 arithmetic);
 // k_interior is a host copy of K's interior coefficients.

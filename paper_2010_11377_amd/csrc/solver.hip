@@ -620,17 +620,17 @@ bool split_ok(const DevOp<T> &D) {
 }
 
 // The nine-point register kernels have the linear interpolation built in.
-bool ws9_usable(const DevOp<float> &D, int nu) {
-  return linear_p(D) && irk::kern::ws9_ok(D.view(), nu);
+template <typename T>
+bool ws9_usable(const DevOp<T> &D, int nu) {
+  return linear_p(D) && irk::kern::ws9_ok<T>(D.view(), nu);
 }
 
 template <typename T>
 void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
   if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sdown(D.view(), D.interior, nu, b, rc, st);
-    if (ws9_usable(D, nu))
-      return irk::kern::s9down(D.view(), D.classes, nu, b, rc, xpre, st);
   }
+  if (ws9_usable<T>(D, nu)) return irk::kern::s9down<T>(D.view(), D.classes, nu, b, rc, xpre, st);
   if (irk::kern::wtile_ok<T>(D.view()))
     irk::kern::wdown<T>(D.view(), nu, b, rc, st);
   else
@@ -642,9 +642,9 @@ void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, 
              hipStream_t st) {
   if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sup(D.view(), D.interior, nu, b, ec, x, st);
-    if (ws9_usable(D, nu))
-      return irk::kern::s9up(D.view(), D.classes, nu, b, ec, xpre, x, st);
   }
+  if (ws9_usable<T>(D, nu))
+    return irk::kern::s9up<T>(D.view(), D.classes, nu, b, ec, xpre, x, st);
   if (irk::kern::wtile_ok<T>(D.view()))
     irk::kern::wup<T>(D.view(), nu, b, ec, x, st);
   else
@@ -772,7 +772,7 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
     const DevOp<T> *D0 = S->lt > 0 ? &Dops<T>(S)[i][0] : nullptr;
     bool ws9_0 = false;  // FP32 nine-point constant-coefficient finest level (M != I)
     if constexpr (std::is_same_v<T, float>)
-      ws9_0 = D0 && !split_ok<T>(*D0) && ws9_usable(*D0, S->opt.nu_pre);
+      ws9_0 = D0 && !split_ok<T>(*D0) && ws9_usable<T>(*D0, S->opt.nu_pre);
     const bool split64 = std::is_same_v<T, double> && D0 && kcouple_ok(S);
     if (S->fine_mode == 2) {
       // K per node: the streaming coupling pass reads K's FP64 arrays

@@ -1,6 +1,6 @@
-// Split-column register tiles for FP32 nine-point levels with constant
+// Split-column register tiles for nine-point levels with constant
 // coefficients per boundary class (the Galerkin coarse levels of the heat
-// hierarchy).  Same layout as the five-point split kernels: lane l holds grid
+// hierarchy), in FP32 (the mixed form) or FP64.  Same layout as the five-point split kernels: lane l holds grid
 // columns X0 + 2l (slot a) and X0 + 2l + 1 (slot b) of R rows; slot a of row
 // r has colour r mod 2.
 //
@@ -41,38 +41,64 @@ __device__ __forceinline__ float nx9(float v) {  // value of lane + 1 (0 in lane
 __device__ __forceinline__ float pv9(float v) {  // value of lane - 1 (0 in lane 0)
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
+__device__ __forceinline__ double nx9(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double pv9(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T>
+struct P9;  // two adjacent elements
+template <>
+struct P9<float> {
+  using V = float2;
+};
+template <>
+struct P9<double> {
+  using V = double2;
+};
 
 // Class q = 3 cy + cx (cx, cy: 0 first, 1 inside, 2 last), coefficient
 // k = 3 (dy + 1) + (dx + 1).  Only compile-time indices are used on the
 // device, so the table stays in the kernel-argument segment.
+template <typename T>
 struct S9Op {
   int nx, ny;
-  float c[9][9];
-  float inv[9];  // 1 / c[q][4]
-  float pw;      // prolongation weight of the outermost fine node
+  T c[9][9];
+  T inv[9];  // 1 / c[q][4]
+  T pw;      // prolongation weight of the outermost fine node
 };
 
-S9Op make_s9op(const OpView<float> &D, const float *classes) {
-  S9Op o;
+template <typename T>
+S9Op<T> make_s9op(const OpView<T> &D, const T *classes) {
+  S9Op<T> o;
   o.nx = D.nx;
   o.ny = D.ny;
   for (int q = 0; q < 9; ++q) {
     for (int k = 0; k < 9; ++k) o.c[q][k] = classes[q * 9 + k];
-    o.inv[q] = 1.0f / o.c[q][4];
+    o.inv[q] = T(1) / o.c[q][4];
   }
   o.pw = D.pw;
   return o;
 }
 
-template <int R>
+template <typename T, int R>
 struct T9 {
-  float xa[R], xb[R], ba[R], bb[R];
+  T xa[R], xb[R], ba[R], bb[R];
 };
 
+template <typename T>
 struct Co {
-  float c[9];
-  float inv;
-  __device__ __forceinline__ float operator[](int k) const { return c[k]; }
+  T c[9];
+  T inv;
+  __device__ __forceinline__ T operator[](int k) const { return c[k]; }
 };
 
 // Per-wave tile placement and boundary flags.
@@ -86,10 +112,10 @@ struct Place {
 
 // The coefficients of slot a (side 0: first-column class when edge) or slot
 // b (side 2: last-column class when edge) for row class CY.
-template <int CY, int SIDE>
-__device__ __forceinline__ Co side_coefs(const S9Op &o, bool edge) {
+template <int CY, int SIDE, typename T>
+__device__ __forceinline__ Co<T> side_coefs(const S9Op<T> &o, bool edge) {
   constexpr int qe = 3 * CY + SIDE, qm = 3 * CY + 1;
-  Co r;
+  Co<T> r;
 #pragma unroll
   for (int k = 0; k < 9; ++k) r.c[k] = edge ? o.c[qe][k] : o.c[qm][k];
   r.inv = edge ? o.inv[qe] : o.inv[qm];
@@ -100,15 +126,18 @@ __device__ __forceinline__ Co side_coefs(const S9Op &o, bool edge) {
 // first row (tile row H when the tile holds it), its last row (tile row
 // H + TY - 1) and every other row.  Selecting them up front keeps the class
 // table out of the registers for the rest of the kernel.
+template <typename T>
 struct RowCo {
-  Co a, b;
+  Co<T> a, b;
 };
+template <typename T>
 struct MidCo {
-  RowCo top, mid, bot;
+  RowCo<T> top, mid, bot;
 };
 
-__device__ __forceinline__ MidCo mid_coefs(const S9Op &o, const Place &p) {
-  MidCo m;
+template <typename T>
+__device__ __forceinline__ MidCo<T> mid_coefs(const S9Op<T> &o, const Place &p) {
+  MidCo<T> m;
   m.mid.a = side_coefs<1, 0>(o, p.fcol);
   m.mid.b = side_coefs<1, 2>(o, p.lcol);
   m.top = m.mid;
@@ -124,20 +153,20 @@ __device__ __forceinline__ MidCo mid_coefs(const S9Op &o, const Place &p) {
   // lanes outside the grid relax with 1 / d = 0, which keeps them at zero
   const int gxa = p.X0 + 2 * l9();
   if (gxa < 0 || gxa >= o.nx) {
-    m.mid.a.inv = m.mid.b.inv = m.top.a.inv = m.top.b.inv = m.bot.a.inv = m.bot.b.inv = 0.0f;
+    m.mid.a.inv = m.mid.b.inv = m.top.a.inv = m.top.b.inv = m.bot.a.inv = m.bot.b.inv = T(0);
   }
   return m;
 }
 
 // sum over the eight neighbours of slot a / slot b in row r
-template <int R, typename C>
-__device__ __forceinline__ float offdiag_a(const C &c, const T9<R> &t, int r) {
+template <typename T, int R, typename C>
+__device__ __forceinline__ T offdiag_a(const C &c, const T9<T, R> &t, int r) {
   return c[0] * pv9(t.xb[r - 1]) + c[1] * t.xa[r - 1] + c[2] * t.xb[r - 1] +
          c[3] * pv9(t.xb[r]) + c[5] * t.xb[r] +
          c[6] * pv9(t.xb[r + 1]) + c[7] * t.xa[r + 1] + c[8] * t.xb[r + 1];
 }
-template <int R, typename C>
-__device__ __forceinline__ float offdiag_b(const C &c, const T9<R> &t, int r) {
+template <typename T, int R, typename C>
+__device__ __forceinline__ T offdiag_b(const C &c, const T9<T, R> &t, int r) {
   return c[0] * t.xa[r - 1] + c[1] * t.xb[r - 1] + c[2] * nx9(t.xa[r - 1]) +
          c[3] * t.xa[r] + c[5] * nx9(t.xa[r]) +
          c[6] * t.xa[r + 1] + c[7] * t.xb[r + 1] + c[8] * nx9(t.xa[r + 1]);
@@ -148,17 +177,17 @@ __device__ __forceinline__ float offdiag_b(const C &c, const T9<R> &t, int r) {
 // < H, 2 those below its last row, tile rows >= H + TY): the grid height is a
 // multiple of TY, so these are the only cases, known at compile time; 3 is
 // both, a single tile row covering the grid).
-template <bool BOUND, int R, int H, int TY, int YB = 0>
+template <typename T, bool BOUND, int R, int H, int TY, int YB = 0>
 struct Ctx {
-  const S9Op &o;
+  const S9Op<T> &o;
   const Place &p;
-  const MidCo &m;
+  const MidCo<T> &m;
   // r is a compile-time row index after unrolling, so these fold to one set
-  __device__ __forceinline__ Co a(int r) const {
+  __device__ __forceinline__ Co<T> a(int r) const {
     if (!BOUND) return side_coefs<1, 1>(o, false);
     return r == H ? m.top.a : (r == H + TY - 1 ? m.bot.a : m.mid.a);
   }
-  __device__ __forceinline__ Co b(int r) const {
+  __device__ __forceinline__ Co<T> b(int r) const {
     if (!BOUND) return side_coefs<1, 1>(o, false);
     return r == H ? m.top.b : (r == H + TY - 1 ? m.bot.b : m.mid.b);
   }
@@ -173,19 +202,20 @@ struct Ctx {
 };
 
 // One colour half sweep over rows [M, R-M), Jacobi within the colour.
-template <bool BOUND, int R, int H, int TY, int YB, int M>
-__device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t, int color) {
-  float pend = 0.0f;
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int M>
+__device__ __forceinline__ void s9_sweep(const Ctx<T, BOUND, R, H, TY, YB> &cx, T9<T, R> &t,
+                                         int color) {
+  T pend = T(0);
 #pragma unroll
   for (int r = M; r < R - M; ++r) {
-    float v = 0.0f;
+    T v = T(0);
     if (cx.row_in(r)) {
       if ((r & 1) == color) {
-        const Co c = cx.a(r);
-        v = (t.ba[r] - offdiag_a<R>(c, t, r)) * c.inv;
+        const Co<T> c = cx.a(r);
+        v = (t.ba[r] - offdiag_a<T, R>(c, t, r)) * c.inv;
       } else {
-        const Co c = cx.b(r);
-        v = (t.bb[r] - offdiag_b<R>(c, t, r)) * c.inv;
+        const Co<T> c = cx.b(r);
+        v = (t.bb[r] - offdiag_b<T, R>(c, t, r)) * c.inv;
       }
     }
     if (r > M) {  // row r-1 is no longer read by this half sweep
@@ -203,53 +233,53 @@ __device__ __forceinline__ void s9_sweep(const Ctx<BOUND, R, H, TY, YB> &cx, T9<
     t.xb[rl] = pend;
 }
 
-template <bool BOUND, int R, int H, int TY, int YB, int NU>
-__device__ __forceinline__ void s9_pre(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t) {
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_pre(const Ctx<T, BOUND, R, H, TY, YB> &cx, T9<T, R> &t) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     // from x = 0 the first colour-0 half sweep is x = b / d (b is zero
     // outside the grid, so this x is too)
     if ((r & 1) == 0) {
       t.xa[r] = t.ba[r] * cx.a(r).inv;
-      t.xb[r] = 0.0f;
+      t.xb[r] = T(0);
     } else {
       t.xb[r] = t.bb[r] * cx.b(r).inv;
-      t.xa[r] = 0.0f;
+      t.xa[r] = T(0);
     }
   }
-  s9_sweep<BOUND, R, H, TY, YB, 1>(cx, t, 1);
+  s9_sweep<T, BOUND, R, H, TY, YB, 1>(cx, t, 1);
   if (NU >= 2) {
-    s9_sweep<BOUND, R, H, TY, YB, 2>(cx, t, 0);
-    s9_sweep<BOUND, R, H, TY, YB, 3>(cx, t, 1);
+    s9_sweep<T, BOUND, R, H, TY, YB, 2>(cx, t, 0);
+    s9_sweep<T, BOUND, R, H, TY, YB, 3>(cx, t, 1);
   }
   if (NU >= 3) {
-    s9_sweep<BOUND, R, H, TY, YB, 4>(cx, t, 0);
-    s9_sweep<BOUND, R, H, TY, YB, 5>(cx, t, 1);
+    s9_sweep<T, BOUND, R, H, TY, YB, 4>(cx, t, 0);
+    s9_sweep<T, BOUND, R, H, TY, YB, 5>(cx, t, 1);
   }
 }
 
 // Post-smoothing in the reverse colour order (colour 1 first), from x exact
 // on the whole tile (the stored pre-smoothed x plus the coarse correction).
-template <bool BOUND, int R, int H, int TY, int YB, int NU>
-__device__ __forceinline__ void s9_post(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t) {
-  s9_sweep<BOUND, R, H, TY, YB, 1>(cx, t, 1);
-  s9_sweep<BOUND, R, H, TY, YB, 2>(cx, t, 0);
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_post(const Ctx<T, BOUND, R, H, TY, YB> &cx, T9<T, R> &t) {
+  s9_sweep<T, BOUND, R, H, TY, YB, 1>(cx, t, 1);
+  s9_sweep<T, BOUND, R, H, TY, YB, 2>(cx, t, 0);
   if (NU >= 2) {
-    s9_sweep<BOUND, R, H, TY, YB, 3>(cx, t, 1);
-    s9_sweep<BOUND, R, H, TY, YB, 4>(cx, t, 0);
+    s9_sweep<T, BOUND, R, H, TY, YB, 3>(cx, t, 1);
+    s9_sweep<T, BOUND, R, H, TY, YB, 4>(cx, t, 0);
   }
   if (NU >= 3) {
-    s9_sweep<BOUND, R, H, TY, YB, 5>(cx, t, 1);
-    s9_sweep<BOUND, R, H, TY, YB, 6>(cx, t, 0);
+    s9_sweep<T, BOUND, R, H, TY, YB, 5>(cx, t, 1);
+    s9_sweep<T, BOUND, R, H, TY, YB, 6>(cx, t, 0);
   }
 }
 
 // rc = R (b - D x), sum over 2 x 2 cells: both slots of one lane, two rows.
 // Writes the coarse nodes of this wave's output rows and lanes.
-template <bool BOUND, int R, int H, int TY, int YB>
-__device__ __forceinline__ void s9_restrict(const Ctx<BOUND, R, H, TY, YB> &cx, const T9<R> &t,
-                                            float *__restrict__ rcoarse) {
-  const S9Op &o = cx.o;
+template <typename T, bool BOUND, int R, int H, int TY, int YB>
+__device__ __forceinline__ void s9_restrict(const Ctx<T, BOUND, R, H, TY, YB> &cx,
+                                            const T9<T, R> &t, T *__restrict__ rcoarse) {
+  const S9Op<T> &o = cx.o;
   const Place &p = cx.p;
   const int lane = l9();
   const int gxa = p.X0 + 2 * lane;
@@ -259,33 +289,34 @@ __device__ __forceinline__ void s9_restrict(const Ctx<BOUND, R, H, TY, YB> &cx, 
   const bool lane_out = lane >= p.lo && lane < p.hi && gxa >= p.OXn && I < ncx;
 #pragma unroll
   for (int r = H; r < R - H; r += 2) {
-    float sum = 0.0f;
+    T sum = T(0);
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const int rr = r + d;
       if (!cx.row_in(rr)) continue;
-      const Co ca = cx.a(rr), cb = cx.b(rr);
-      const float ra = t.ba[rr] - ca.c[4] * t.xa[rr] - offdiag_a<R>(ca, t, rr);
-      const float rb = t.bb[rr] - cb.c[4] * t.xb[rr] - offdiag_b<R>(cb, t, rr);
+      const Co<T> ca = cx.a(rr), cb = cx.b(rr);
+      const T ra = t.ba[rr] - ca.c[4] * t.xa[rr] - offdiag_a<T, R>(ca, t, rr);
+      const T rb = t.bb[rr] - cb.c[4] * t.xb[rr] - offdiag_b<T, R>(cb, t, rr);
       sum += ra + rb;
     }
     // an outside node next to an inside one has a nonzero residual
-    if (!inx) sum = 0.0f;
+    if (!inx) sum = T(0);
     const int gy0 = p.Y0 + r, J = gy0 >> 1;
     if (lane_out && gy0 >= p.OYn && J < ncy) rcoarse[(size_t)J * ncx + I] = sum;
   }
 }
 
-template <int R>
-__device__ __forceinline__ void s9_load(const float *__restrict__ g, float (&a)[R], float (&b)[R],
-                                        int X0, int Y0, int nx, int ny) {
+template <typename T, int R>
+__device__ __forceinline__ void s9_load(const T *__restrict__ g, T (&a)[R], T (&b)[R], int X0,
+                                        int Y0, int nx, int ny) {
+  using V = typename P9<T>::V;
   const int gx = X0 + 2 * l9();
   const bool inx = gx >= 0 && gx < nx;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int gy = Y0 + r;
-    float2 v = make_float2(0.0f, 0.0f);
-    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const float2 *>(g + (size_t)gy * nx + gx);
+    V v{};
+    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const V *>(g + (size_t)gy * nx + gx);
     a[r] = v.x;
     b[r] = v.y;
   }
@@ -313,8 +344,8 @@ static_assert(kTY9 > ev9(2 * 3), "tile height must exceed the row halo for nu <=
 
 // Placement of this wave's tile; false if the wave has no rows.  Needs
 // nx >= TXO and ny a multiple of TY.
-template <typename G>
-__device__ __forceinline__ bool place(const S9Op &o, Place &p) {
+template <typename G, typename T>
+__device__ __forceinline__ bool place(const S9Op<T> &o, Place &p) {
   const int wave = threadIdx.x >> 6;
   const Tile2 tile = xcd_tile();
   p.OXn = tile.x * G::TXO;
@@ -337,55 +368,59 @@ __device__ __forceinline__ bool boundary_tile(const Place &p, int R, int nx, int
   return !(p.X0 >= 1 && p.Y0 >= 1 && p.X0 + 128 <= nx - 1 && p.Y0 + R <= ny - 1);
 }
 
-template <bool BOUND, int R, int H, int TY, int YB, int NU>
-__device__ __forceinline__ void s9_down_tile(const S9Op &o, const Place &p, const MidCo &m,
-                                             T9<R> &t, float *__restrict__ rc) {
-  const Ctx<BOUND, R, H, TY, YB> cx{o, p, m};
-  s9_pre<BOUND, R, H, TY, YB, NU>(cx, t);
-  s9_restrict<BOUND, R, H, TY, YB>(cx, t, rc);
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_down_tile(const S9Op<T> &o, const Place &p, const MidCo<T> &m,
+                                             T9<T, R> &t, T *__restrict__ rc) {
+  const Ctx<T, BOUND, R, H, TY, YB> cx{o, p, m};
+  s9_pre<T, BOUND, R, H, TY, YB, NU>(cx, t);
+  s9_restrict<T, BOUND, R, H, TY, YB>(cx, t, rc);
 }
 
 // Pre-smoothing from zero and rc = R (b - D x); the pre-smoothed x of the
 // output region goes to xpre for the up pass.
-template <int NU, int TY>
+template <typename T, int NU, int TY>
 __global__ void __launch_bounds__(64 * kW9)
-    k_s9down(S9Op o, const float *__restrict__ bin, float *__restrict__ rc,
-             float *__restrict__ xpre) {
+    k_s9down(S9Op<T> o, const T *__restrict__ bin, T *__restrict__ rc, T *__restrict__ xpre) {
   using G = G9<NU, TY, false>;
+  using V = typename P9<T>::V;
   constexpr int H = G::H, R = G::R;
   Place p;
   if (!place<G>(o, p)) return;
-  T9<R> t;
-  s9_load<R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
+  T9<T, R> t;
+  s9_load<T, R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
   if (!boundary_tile(p, R, o.nx, o.ny)) {
-    s9_down_tile<false, R, H, TY, 0, NU>(o, p, MidCo{}, t, rc);
+    s9_down_tile<T, false, R, H, TY, 0, NU>(o, p, MidCo<T>{}, t, rc);
   } else {
-    const MidCo m = mid_coefs(o, p);
+    const MidCo<T> m = mid_coefs(o, p);
     if (p.top && p.bot)
-      s9_down_tile<true, R, H, TY, 3, NU>(o, p, m, t, rc);
+      s9_down_tile<T, true, R, H, TY, 3, NU>(o, p, m, t, rc);
     else if (p.top)
-      s9_down_tile<true, R, H, TY, 1, NU>(o, p, m, t, rc);
+      s9_down_tile<T, true, R, H, TY, 1, NU>(o, p, m, t, rc);
     else if (p.bot)
-      s9_down_tile<true, R, H, TY, 2, NU>(o, p, m, t, rc);
+      s9_down_tile<T, true, R, H, TY, 2, NU>(o, p, m, t, rc);
     else
-      s9_down_tile<true, R, H, TY, 0, NU>(o, p, m, t, rc);
+      s9_down_tile<T, true, R, H, TY, 0, NU>(o, p, m, t, rc);
   }
   const int lane = l9(), gxa = p.X0 + 2 * lane;
   if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
 #pragma unroll
     for (int r = H; r < R - H; ++r) {
       const int gy = p.Y0 + r;
-      if (gy < o.ny)
-        *reinterpret_cast<float2 *>(xpre + (size_t)gy * o.nx + gxa) = make_float2(t.xa[r], t.xb[r]);
+      if (gy < o.ny) {
+        V v;
+        v.x = t.xa[r];
+        v.y = t.xb[r];
+        *reinterpret_cast<V *>(xpre + (size_t)gy * o.nx + gxa) = v;
+      }
     }
   }
 }
 
 // x = xpre + P e_c, then the post-smoothing.
-template <bool BOUND, int R, int H, int TY, int YB, int NU>
-__device__ __forceinline__ void s9_up_body(const Ctx<BOUND, R, H, TY, YB> &cx, T9<R> &t,
-                                           const float (&cr)[R / 2 + 3]) {
-  const S9Op &o = cx.o;
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_up_body(const Ctx<T, BOUND, R, H, TY, YB> &cx, T9<T, R> &t,
+                                           const T (&cr)[R / 2 + 3]) {
+  const S9Op<T> &o = cx.o;
   // fine column 2I takes 3/4 of coarse column I and 1/4 of I-1, column 2I+1
   // 3/4 of I and 1/4 of I+1, likewise in y; the outermost fine column / row
   // takes pw of its coarse node (its second coarse node is outside the grid,
@@ -393,74 +428,79 @@ __device__ __forceinline__ void s9_up_body(const Ctx<BOUND, R, H, TY, YB> &cx, T
   const int gxa = cx.p.X0 + 2 * l9();
   const bool inx = cx.lane_in();
   // lanes outside the grid take no correction
-  const float wxa = !inx ? 0.0f : (gxa == 0 ? o.pw : 0.75f);
-  const float wxb = !inx ? 0.0f : (gxa + 2 == o.nx ? o.pw : 0.75f);
-  const float wq = !inx ? 0.0f : 0.25f;
+  const T wxa = !inx ? T(0) : (gxa == 0 ? o.pw : T(0.75));
+  const T wxb = !inx ? T(0) : (gxa + 2 == o.nx ? o.pw : T(0.75));
+  const T wq = !inx ? T(0) : T(0.25);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (!cx.row_in(r)) continue;
     const int gy = cx.p.Y0 + r;
-    const float wy = (gy == 0 || gy == o.ny - 1) ? o.pw : 0.75f;
-    const float cj = cr[r / 2 + 1];
-    const float cn = cr[(r & 1) ? r / 2 + 2 : r / 2];
-    const float ya = wy * cj + 0.25f * cn;
-    const float yp = wy * pv9(cj) + 0.25f * pv9(cn);
-    const float yn = wy * nx9(cj) + 0.25f * nx9(cn);
+    const T wy = (gy == 0 || gy == o.ny - 1) ? o.pw : T(0.75);
+    const T cj = cr[r / 2 + 1];
+    const T cn = cr[(r & 1) ? r / 2 + 2 : r / 2];
+    const T ya = wy * cj + T(0.25) * cn;
+    const T yp = wy * pv9(cj) + T(0.25) * pv9(cn);
+    const T yn = wy * nx9(cj) + T(0.25) * nx9(cn);
     t.xa[r] += wxa * ya + wq * yp;
     t.xb[r] += wxb * ya + wq * yn;
   }
-  s9_post<BOUND, R, H, TY, YB, NU>(cx, t);
+  s9_post<T, BOUND, R, H, TY, YB, NU>(cx, t);
 }
 
-template <bool BOUND, int R, int H, int TY, int YB, int NU>
-__device__ __forceinline__ void s9_up_tile(const S9Op &o, const Place &p, const MidCo &m,
-                                           T9<R> &t, const float (&cr)[R / 2 + 3]) {
-  const Ctx<BOUND, R, H, TY, YB> cx{o, p, m};
-  s9_up_body<BOUND, R, H, TY, YB, NU>(cx, t, cr);
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_up_tile(const S9Op<T> &o, const Place &p, const MidCo<T> &m,
+                                           T9<T, R> &t, const T (&cr)[R / 2 + 3]) {
+  const Ctx<T, BOUND, R, H, TY, YB> cx{o, p, m};
+  s9_up_body<T, BOUND, R, H, TY, YB, NU>(cx, t, cr);
 }
 
-template <int NU, int TY>
+template <typename T, int NU, int TY>
 __global__ void __launch_bounds__(64 * kW9)
-    k_s9up(S9Op o, const float *__restrict__ bin, const float *__restrict__ ec,
-           const float *__restrict__ xpre, float *__restrict__ xout) {
+    k_s9up(S9Op<T> o, const T *__restrict__ bin, const T *__restrict__ ec,
+           const T *__restrict__ xpre, T *__restrict__ xout) {
   using G = G9<NU, TY, true>;
+  using V = typename P9<T>::V;
   constexpr int H = G::H, R = G::R;
   Place p;
   if (!place<G>(o, p)) return;
   const int lane = l9();
   const int ncx = o.nx / 2, ncy = o.ny / 2;
-  T9<R> t;
-  s9_load<R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
-  s9_load<R>(xpre, t.xa, t.xb, p.X0, p.Y0, o.nx, o.ny);
-  float cr[R / 2 + 3];
+  T9<T, R> t;
+  s9_load<T, R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
+  s9_load<T, R>(xpre, t.xa, t.xb, p.X0, p.Y0, o.nx, o.ny);
+  T cr[R / 2 + 3];
   {
     const int I = (p.X0 >> 1) + lane;
 #pragma unroll
     for (int q = 0; q < R / 2 + 3; ++q) {
       const int J = (p.Y0 >> 1) - 1 + q;
-      cr[q] = (I >= 0 && I < ncx && J >= 0 && J < ncy) ? ec[(size_t)J * ncx + I] : 0.0f;
+      cr[q] = (I >= 0 && I < ncx && J >= 0 && J < ncy) ? ec[(size_t)J * ncx + I] : T(0);
     }
   }
   if (!boundary_tile(p, R, o.nx, o.ny)) {
-    s9_up_tile<false, R, H, TY, 0, NU>(o, p, MidCo{}, t, cr);
+    s9_up_tile<T, false, R, H, TY, 0, NU>(o, p, MidCo<T>{}, t, cr);
   } else {
-    const MidCo m = mid_coefs(o, p);
+    const MidCo<T> m = mid_coefs(o, p);
     if (p.top && p.bot)
-      s9_up_tile<true, R, H, TY, 3, NU>(o, p, m, t, cr);
+      s9_up_tile<T, true, R, H, TY, 3, NU>(o, p, m, t, cr);
     else if (p.top)
-      s9_up_tile<true, R, H, TY, 1, NU>(o, p, m, t, cr);
+      s9_up_tile<T, true, R, H, TY, 1, NU>(o, p, m, t, cr);
     else if (p.bot)
-      s9_up_tile<true, R, H, TY, 2, NU>(o, p, m, t, cr);
+      s9_up_tile<T, true, R, H, TY, 2, NU>(o, p, m, t, cr);
     else
-      s9_up_tile<true, R, H, TY, 0, NU>(o, p, m, t, cr);
+      s9_up_tile<T, true, R, H, TY, 0, NU>(o, p, m, t, cr);
   }
   const int gxa = p.X0 + 2 * lane;
   if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
 #pragma unroll
     for (int r = H; r < R - H; ++r) {
       const int gy = p.Y0 + r;
-      if (gy < o.ny)
-        *reinterpret_cast<float2 *>(xout + (size_t)gy * o.nx + gxa) = make_float2(t.xa[r], t.xb[r]);
+      if (gy < o.ny) {
+        V v;
+        v.x = t.xa[r];
+        v.y = t.xb[r];
+        *reinterpret_cast<V *>(xout + (size_t)gy * o.nx + gxa) = v;
+      }
     }
   }
 }
@@ -488,34 +528,49 @@ bool level_ok(int nx, int ny) {
   return geometry_ok<G9<NU, kTY9, false>>(nx, ny) && geometry_ok<G9<NU, kTY9, true>>(nx, ny);
 }
 
-bool ws9_ok(const OpView<float> &D, int nu) {
+template <typename T>
+bool ws9_ok(const OpView<T> &D, int nu) {
   if (D.npt != 9 || !D.cls || D.arr) return false;
   if (nu == 1) return level_ok<1>(D.nx, D.ny);
   if (nu == 2) return level_ok<2>(D.nx, D.ny);
   return level_ok<3>(D.nx, D.ny);
 }
 
-#define IRK_S9_NU(KERNEL, UP, ...)                                                           \
-  do {                                                                                       \
-    if (nu == 1)                                                                             \
-      KERNEL<1, kTY9><<<grid9<G9<1, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__);  \
-    else if (nu == 2)                                                                        \
-      KERNEL<2, kTY9><<<grid9<G9<2, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__);  \
-    else                                                                                     \
-      KERNEL<3, kTY9><<<grid9<G9<3, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__);  \
+template bool ws9_ok<float>(const OpView<float> &, int);
+template bool ws9_ok<double>(const OpView<double> &, int);
+
+#define IRK_S9_NU(KERNEL, UP, ...)                                                             \
+  do {                                                                                         \
+    if (nu == 1)                                                                               \
+      KERNEL<T, 1, kTY9><<<grid9<G9<1, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__); \
+    else if (nu == 2)                                                                          \
+      KERNEL<T, 2, kTY9><<<grid9<G9<2, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__); \
+    else                                                                                       \
+      KERNEL<T, 3, kTY9><<<grid9<G9<3, kTY9, UP>>(o.nx, o.ny), 64 * kW9, 0, st>>>(__VA_ARGS__); \
   } while (0)
 
-void s9down(const OpView<float> &D, const float *classes, int nu, const float *b, float *rc,
-            float *xpre, hipStream_t st) {
-  const S9Op o = make_s9op(D, classes);
+template <typename T>
+void s9down(const OpView<T> &D, const T *classes, int nu, const T *b, T *rc, T *xpre,
+            hipStream_t st) {
+  const S9Op<T> o = make_s9op(D, classes);
   IRK_S9_NU(k_s9down, false, o, b, rc, xpre);
 }
 
-void s9up(const OpView<float> &D, const float *classes, int nu, const float *b, const float *ec,
-          const float *xpre, float *x, hipStream_t st) {
-  const S9Op o = make_s9op(D, classes);
+template <typename T>
+void s9up(const OpView<T> &D, const T *classes, int nu, const T *b, const T *ec, const T *xpre,
+          T *x, hipStream_t st) {
+  const S9Op<T> o = make_s9op(D, classes);
   IRK_S9_NU(k_s9up, true, o, b, ec, xpre, x);
 }
+
+template void s9down<float>(const OpView<float> &, const float *, int, const float *, float *,
+                            float *, hipStream_t);
+template void s9down<double>(const OpView<double> &, const double *, int, const double *,
+                             double *, double *, hipStream_t);
+template void s9up<float>(const OpView<float> &, const float *, int, const float *, const float *,
+                          const float *, float *, hipStream_t);
+template void s9up<double>(const OpView<double> &, const double *, int, const double *,
+                           const double *, const double *, double *, hipStream_t);
 
 }  // namespace kern
 }  // namespace irk
