@@ -405,14 +405,21 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
     S->lnx.push_back(Sl[l].nx);
     S->lny.push_back(Sl[l].ny);
   }
-  // the tail starts at the first level that fits one workgroup's LDS (<= 64 KiB)
+  // the tail starts at the first level that fits one workgroup's LDS (the
+  // device's limit per workgroup: 160 KiB on gfx950; 64 KiB if unknown)
   {
     const size_t es = (S->opt.precision == IRK_MIXED) ? 4 : 8;
+    int dev = 0, lds = 0;
+    size_t lds_max = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds > 65536)
+      lds_max = (size_t)lds;
     S->lt = L - 1;
     for (int l = 0; l < L; ++l) {
       size_t words = 1024 + 81 * (size_t)(L - l);  // reduction buffer + class tables
       for (int m = l; m < L; ++m) words += 2 * (size_t)Sl[m].nx * Sl[m].ny;
-      if ((size_t)Sl[l].nx * Sl[l].ny <= (size_t)irk::kTailMax && words * es <= 65536 &&
+      if ((size_t)Sl[l].nx * Sl[l].ny <= (size_t)irk::kTailMax && words * es <= lds_max &&
           L - l <= irk::kTailLevels) {
         S->lt = l;
         break;
