@@ -87,6 +87,7 @@ enum { IRK_FP64 = 0, IRK_MIXED = 1 };
 enum { IRK_PREC_LD = 0, IRK_PREC_DU = 1, IRK_PREC_GSL = 2, IRK_PREC_J = 3 };
 enum { IRK_RIGHT = 0, IRK_LEFT = 1 };
 enum { IRK_INTERP_LINEAR = 0, IRK_INTERP_CONSTANT = 1 };
+enum { IRK_SMOOTH_RBGS = 0, IRK_SMOOTH_JACOBI = 1 };
 
 typedef struct {
   int precision;   /* IRK_FP64: everything in double.  IRK_MIXED: V-cycles,
@@ -96,7 +97,8 @@ typedef struct {
   int precond;     /* IRK_PREC_LD (the paper's method), DU, GSL or J */
   int restart;     /* FGMRES restart length m (1..200) */
   int max_iter;    /* total Krylov iterations allowed per solve */
-  int nu_pre;      /* red-black Gauss-Seidel sweeps before the coarse correction (1..3) */
+  int nu_pre;      /* smoothing sweeps before the coarse correction (1..3): red-black
+                      Gauss-Seidel sweeps (both colours) or damped Jacobi sweeps */
   int nu_post;     /* sweeps after it (must equal nu_pre) */
   int coarse_max;  /* coarsen while the level has more unknowns than this */
   int vcycles;     /* V-cycles per diagonal-block subsolve (the paper uses 1) */
@@ -136,6 +138,12 @@ typedef struct {
                       and post-smoothing with no coarse correction, and the
                       levels below it are skipped for that block.  0: every
                       cycle goes down to the coarsest level (solved exactly). */
+  int smoother;    /* IRK_SMOOTH_RBGS: red-black Gauss-Seidel (colours 0, 1
+                      before the coarse correction, 1, 0 after; Jacobi within
+                      a colour on nine-point levels), the default.
+                      IRK_SMOOTH_JACOBI: damped Jacobi x += jacobi_omega
+                      D^-1 (b - D x), every node from the old values. */
+  double jacobi_omega; /* Jacobi damping weight in (0, 1] (default 0.8) */
 } irk_options;
 
 typedef struct {
@@ -149,7 +157,7 @@ typedef struct {
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
  * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR,
- * graphs 0, coarse_ratio 2. */
+ * graphs 0, coarse_ratio 2, smoother IRK_SMOOTH_RBGS, jacobi_omega 0.8. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.

@@ -26,6 +26,7 @@ IRK_RIGHT = 0
 IRK_LEFT = 1
 IRK_INTERP_LINEAR = 0
 IRK_INTERP_CONSTANT = 1
+SMOOTHER = {"rbgs": 0, "jacobi": 1}
 PRECOND = {"LD": 0, "DU": 1, "GSL": 2, "J": 3}
 
 
@@ -51,7 +52,8 @@ class Options(ctypes.Structure):
                 ("true_resid", ctypes.c_int), ("reorth", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("side", ctypes.c_int),
                 ("interp", ctypes.c_int), ("graphs", ctypes.c_int),
-                ("coarse_ratio", ctypes.c_double)]
+                ("coarse_ratio", ctypes.c_double), ("smoother", ctypes.c_int),
+                ("jacobi_omega", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

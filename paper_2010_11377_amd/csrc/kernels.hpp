@@ -50,6 +50,7 @@ struct OpView {
   T pw;            // prolongation weight of an outermost fine node from its parent
   T pa = T(0.75);  // prolongation weight from the parent (other fine nodes)
   T pn = T(0.25);  // prolongation weight from the next coarse node (0: piecewise constant)
+  T jw = T(0);     // smoother: 0 red-black Gauss-Seidel; > 0 damped Jacobi with this weight
 };
 
 // The coarse end of the hierarchy, solved by one workgroup in LDS: levels
@@ -69,6 +70,7 @@ struct TailDesc {
   T pw[kTailLevels];  // prolongation boundary weight of level l (see OpView)
   T pa = T(0.75), pn = T(0.25);  // parent / next-node prolongation weights (see OpView)
   const T *CinvT;  // null: the coarsest level returns x = 0 (the cycle ends one level up)
+  T jw = T(0);     // smoother (see OpView)
 };
 
 // The finest level of the stage blocks D_i = I + tau_i K (M = I) for the

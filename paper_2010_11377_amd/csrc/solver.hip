@@ -41,7 +41,8 @@ struct DevOp {
   T classes[81] = {};  // host copy of all nine classes (q * 9 + k)
   T pw = T(0);         // prolongation boundary weight of this level
   T pa = T(0.75), pn = T(0.25);  // parent and next-node weights (linear interpolation)
-  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform, pw, pa, pn}; }
+  T jw = T(0);                   // smoother: 0 red-black Gauss-Seidel, > 0 damped Jacobi weight
+  OpView<T> view() const { return OpView<T>{nx, ny, npt, cls, arr, uniform, pw, pa, pn, jw}; }
 };
 
 // A constant-coefficient operator is uniform when every boundary class equals
@@ -159,6 +160,9 @@ struct irk_solver {
 namespace {
 
 size_t elem_size(const irk_solver *S) { return S->opt.precision == IRK_MIXED ? 4 : 8; }
+
+// The V-cycles smooth with damped Jacobi (else red-black Gauss-Seidel).
+bool jacobi(const irk_solver *S) { return S->opt.smoother == IRK_SMOOTH_JACOBI; }
 
 using ProfTok = irk_solver::ProfTok;
 
@@ -446,18 +450,21 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
       Stencil9 D = irk::axpy_stencil(Sl[l], S->tau[i], Kl[l]);
       const int npt = stencil_npt(D);
       const irk::Interp ip = interp_of(S, l);
+      const double jw = S->opt.smoother == IRK_SMOOTH_JACOBI ? S->opt.jacobi_omega : 0.0;
       if (mixed) {
         S->D32[i].push_back(upload_op<float>(S, D, cm, npt));
         DevOp<float> &d = S->D32[i].back();
         d.pw = (float)ip.wb;
         d.pa = (float)ip.own;
         d.pn = (float)ip.nb;
+        d.jw = (float)jw;
       } else {
         S->D64[i].push_back(upload_op<double>(S, D, cm, npt));
         DevOp<double> &d = S->D64[i].back();
         d.pw = ip.wb;
         d.pa = ip.own;
         d.pn = ip.nb;
+        d.jw = jw;
       }
     }
     Stencil9 Dc = irk::axpy_stencil(Sl[L - 1], S->tau[i], Kl[L - 1]);
@@ -634,6 +641,7 @@ bool ws9_usable(const DevOp<T> &D, int nu) {
 
 template <typename T>
 void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
+  if (D.jw > T(0)) return irk::kern::vdown<T>(D.view(), nu, b, rc, st);  // damped Jacobi
   if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sdown(D.view(), D.interior, nu, b, rc, st);
   }
@@ -647,6 +655,7 @@ void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_
 template <typename T>
 void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, T *x,
              hipStream_t st) {
+  if (D.jw > T(0)) return irk::kern::vup<T>(D.view(), nu, b, ec, x, st);  // damped Jacobi
   if constexpr (std::is_same_v<T, float>) {
     if (split_ok(D)) return irk::kern::sup(D.view(), D.interior, nu, b, ec, x, st);
   }
@@ -679,7 +688,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   for (int l = finest_down_done ? 1 : 0; l < lt; ++l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
-    if (l == 0 && S->fine_mode) {
+    if (l == 0 && S->fine_mode && !jacobi(S)) {
       // b and K per node (read) in, the coarse residual and the pre-smoothed x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
       ProfTok t = prof_begin(S, IRK_KC_VDOWN_L0, (double)n * es * 2.25 + kb);
@@ -715,12 +724,13 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     td.off[td.nlev] = off;
     // a cycle that ends inside the tail: its coarsest level returns zero
     td.CinvT = ends ? nullptr : Cinv<T>(S, i);
+    td.jw = jacobi(S) ? (T)S->opt.jacobi_omega : T(0);
     const size_t ntop = (size_t)S->lnx[lt] * S->lny[lt];
     words += 2 * ntop + (ends ? 0 : (size_t)S->ncoarse * S->ncoarse);
     ProfTok t = prof_begin(S, IRK_KC_VTAIL, (double)words * es);
     bool done = false;
     if constexpr (std::is_same_v<T, float>) {
-      if (irk::kern::vtail2_ok(td)) {
+      if (!jacobi(S) && irk::kern::vtail2_ok(td)) {
         irk::kern::vtail2(td, nu, bl(lt), xl(lt), st);
         done = true;
       }
@@ -731,7 +741,7 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   for (int l = lt - 1; l >= 0; --l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
-    if (l == 0 && S->fine_mode) {
+    if (l == 0 && S->fine_mode && !jacobi(S)) {
       // b, the pre-smoothed x, K per node and the coarse correction in, x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
       ProfTok t = prof_begin(S, IRK_KC_VUP_L0, (double)n * es * 3.25 + kb);
@@ -797,7 +807,7 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
       couple_split<T>(S, v, scale_j, z, C + (size_t)i * S->s, i);
       prof_end(S, tk);
       vcycle<T>(S, i, b0, z + (size_t)i * N, false);
-    } else if (D0 && !ws9_0 && !std::is_same_v<T, double>) {
+    } else if (D0 && !ws9_0 && !std::is_same_v<T, double> && !jacobi(S)) {
       // coupling fused into the finest-level down pass (+ rc = R(b - D x))
       const DevOp<T> &D = *D0;
       ProfTok tk = prof_begin(S, IRK_KC_VDOWN_L0,
@@ -1223,6 +1233,10 @@ bool valid_options(const irk_options &o, std::string &err) {
     return err = "coarse_ratio must be finite and >= 0", false;
   if (o.side == IRK_LEFT && o.precision != IRK_FP64)
     return err = "left preconditioning needs precision IRK_FP64", false;
+  if (o.smoother != IRK_SMOOTH_RBGS && o.smoother != IRK_SMOOTH_JACOBI)
+    return err = "smoother must be IRK_SMOOTH_RBGS or IRK_SMOOTH_JACOBI", false;
+  if (o.smoother == IRK_SMOOTH_JACOBI && !(o.jacobi_omega > 0.0 && o.jacobi_omega <= 1.0))
+    return err = "jacobi_omega must be in (0, 1]", false;
   return true;
 }
 
@@ -1385,6 +1399,8 @@ void irk_default_options(irk_options *o) {
   o->interp = IRK_INTERP_LINEAR;
   o->graphs = 0;
   o->coarse_ratio = 2.0;
+  o->smoother = IRK_SMOOTH_RBGS;
+  o->jacobi_omega = 0.8;
 }
 
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {

@@ -1,7 +1,9 @@
 // Fused AMG V-cycle kernels (gfx950).
 //
 // One V(nu, nu) cycle on a stage block D = S_l + tau K_l (Sec. 4.2: one
-// V-cycle per diagonal block) with red-black Gauss-Seidel smoothing, from a
+// V-cycle per diagonal block) with red-black Gauss-Seidel smoothing (or, with
+// OpView::jw > 0, damped Jacobi: x += jw D^-1 (b - A x), every node from the
+// old values, nu sweeps before and after the coarse correction), from a
 // zero initial guess.  The smoother is the memory-bound part, so several
 // sweeps are fused into one pass over HBM with LDS temporal blocking: a tile
 // of the grid plus a halo is staged in LDS, every sweep shrinks the region
@@ -144,6 +146,41 @@ __device__ __forceinline__ void tile_sweep(const OpView<T> &D, const T *cls_lds,
   }
 }
 
+// One damped Jacobi sweep over the LDS region [m, W-m) x [m, HH-m): every
+// grid node takes x + jw (b - A x) / d from the old values (computed into
+// registers, written after a barrier).
+template <typename T, int NPT, bool CLS, int W, int HH, int NT>
+__device__ __forceinline__ void tile_jsweep(const OpView<T> &D, const T *cls_lds, const T *ci,
+                                            T *sx, const T *sb, int X0, int Y0, int m) {
+  const int w = W - 2 * m, hgt = HH - 2 * m;
+  constexpr int MAXP = (W * HH + NT - 1) / NT;
+  T nv[MAXP];
+#pragma unroll
+  for (int it = 0; it < MAXP; ++it) {
+    const int q = threadIdx.x + it * NT;
+    nv[it] = T(0);
+    if (q >= w * hgt) continue;
+    const int lx = m + q % w, ly = m + q / w;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    if (gx < 0 || gy < 0 || gx >= D.nx || gy >= D.ny) continue;
+    T a[9];
+    node_coefs<T, NPT, CLS>(cls_lds, ci, D, gx, gy, a);
+    const T xo = sx[ly * W + lx];
+    nv[it] = xo + D.jw * ((offdiag_rhs<T, NPT, W>(a, sx, sb, lx, ly) - a[4] * xo) / a[4]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < MAXP; ++it) {
+    const int q = threadIdx.x + it * NT;
+    if (q >= w * hgt) continue;
+    const int lx = m + q % w, ly = m + q / w;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    if (gx < 0 || gy < 0 || gx >= D.nx || gy >= D.ny) continue;
+    sx[ly * W + lx] = nv[it];
+  }
+  __syncthreads();
+}
+
 // Stage a grid vector on the LDS region whose origin is grid node (X0, Y0),
 // zero outside the grid.  A plain copy loop, so that many loads are in flight.
 template <typename T, int W, int HH, int NT>
@@ -158,9 +195,16 @@ __device__ __forceinline__ void tile_load(const T *__restrict__ g, T *lds, int X
 
 // x = 0 followed by the first half sweep (colour 0 gets b / d), then the
 // remaining 2 nu - 1 half sweeps.  Afterwards x is exact on margin >= 2nu-1.
-template <typename T, int NPT, bool CLS, int NU, int W, int HH, int NT>
+template <typename T, int NPT, bool CLS, int NU, int W, int HH, int NT, bool JAC = false>
 __device__ __forceinline__ void tile_presmooth(const OpView<T> &D, const T *cls_lds, const T *ci, T *sx,
                                                const T *sb, int X0, int Y0) {
+  if constexpr (JAC) {
+    // Jacobi from x = 0: nu sweeps, exact on margin nu afterwards
+    for (int q = threadIdx.x; q < W * HH; q += NT) sx[q] = T(0);
+    __syncthreads();
+    for (int k = 1; k <= NU; ++k) tile_jsweep<T, NPT, CLS, W, HH, NT>(D, cls_lds, ci, sx, sb, X0, Y0, k);
+    return;
+  }
   for (int q = threadIdx.x; q < W * HH; q += NT) {
     const int gx = X0 + q % W, gy = Y0 + q / W;
     T xv = T(0);
@@ -203,7 +247,7 @@ __device__ __forceinline__ void tile_restrict(const OpView<T> &D, const T *cls_l
 
 constexpr int kNT = 256;
 
-template <typename T, int NPT, bool CLS, int NU, int TX, int TY>
+template <typename T, int NPT, bool CLS, int NU, int TX, int TY, bool JAC>
 __global__ void __launch_bounds__(kNT)
     k_vdown(OpView<T> D, const T *__restrict__ b, T *__restrict__ rc) {
   constexpr int H = 2 * NU;
@@ -218,7 +262,7 @@ __global__ void __launch_bounds__(kNT)
   __syncthreads();
   T ci[9];
   interior_coefs<T, CLS>(scls, ci);
-  tile_presmooth<T, NPT, CLS, NU, W, HH, kNT>(D, scls, ci, sx, sb, X0, Y0);
+  tile_presmooth<T, NPT, CLS, NU, W, HH, kNT, JAC>(D, scls, ci, sx, sb, X0, Y0);
   tile_restrict<T, NPT, CLS, TX, TY, H, W, kNT>(D, scls, ci, sx, sb, X0, Y0, rc);
 }
 
@@ -321,7 +365,7 @@ __device__ __forceinline__ T prolong_value(const T *ec, int CW, int CX0, int CY0
   return v;
 }
 
-template <typename T, int NPT, bool CLS, int NU, int TX, int TY>
+template <typename T, int NPT, bool CLS, int NU, int TX, int TY, bool JAC>
 __global__ void __launch_bounds__(kNT)
     k_vup(OpView<T> D, const T *__restrict__ b, const T *__restrict__ ec, T *__restrict__ x) {
   constexpr int H = 4 * NU - 1;
@@ -343,7 +387,7 @@ __global__ void __launch_bounds__(kNT)
   __syncthreads();
   T ci[9];
   interior_coefs<T, CLS>(scls, ci);
-  tile_presmooth<T, NPT, CLS, NU, W, HH, kNT>(D, scls, ci, sx, sb, X0, Y0);
+  tile_presmooth<T, NPT, CLS, NU, W, HH, kNT, JAC>(D, scls, ci, sx, sb, X0, Y0);
   {
     constexpr int w = W - 2 * m, hgt = HH - 2 * m;
     for (int q = threadIdx.x; q < w * hgt; q += kNT) {
@@ -354,9 +398,14 @@ __global__ void __launch_bounds__(kNT)
     }
     __syncthreads();
   }
+  if constexpr (JAC) {
+    for (int k = 0; k < NU; ++k)
+      tile_jsweep<T, NPT, CLS, W, HH, kNT>(D, scls, ci, sx, sb, X0, Y0, 2 * NU + k);
+  } else {
 #pragma unroll
-  for (int k = 0; k < 2 * NU; ++k)
-    tile_sweep<T, NPT, CLS, W, HH, kNT>(D, scls, ci, sx, sb, X0, Y0, (k & 1) ^ 1, 2 * NU + k);
+    for (int k = 0; k < 2 * NU; ++k)
+      tile_sweep<T, NPT, CLS, W, HH, kNT>(D, scls, ci, sx, sb, X0, Y0, (k & 1) ^ 1, 2 * NU + k);
+  }
   for (int q = threadIdx.x; q < TX * TY; q += kNT) {
     const int lx = H + q % TX, ly = H + q / TX;
     const int gx = X0 + lx, gy = Y0 + ly;
@@ -419,7 +468,30 @@ __device__ void tail_sweep(const TailDesc<T> &td, const T *cls_lds, int l, T *sx
   __syncthreads();
 }
 
+// One damped Jacobi sweep of a tail level (every node from the old values).
 template <typename T, bool CLS>
+__device__ void tail_jsweep(const TailDesc<T> &td, const T *cls_lds, int l, T *sx, const T *sb) {
+  const int nx = td.nx[l], ny = td.ny[l], n = nx * ny;
+  T nv[2 * kTailPer];
+#pragma unroll
+  for (int it = 0; it < 2 * kTailPer; ++it) {
+    const int p = threadIdx.x + it * kTailThreads;
+    nv[it] = T(0);
+    if (p >= n) continue;
+    const int i = p % nx, j = p / nx;
+    // x + jw (b - D x) / d = x + jw ((b - offdiag x) / d - x)
+    nv[it] = sx[p] + td.jw * (tail_node<T, CLS>(td, cls_lds, l, sx, sb, i, j, false) - sx[p]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < 2 * kTailPer; ++it) {
+    const int p = threadIdx.x + it * kTailThreads;
+    if (p < n) sx[p] = nv[it];
+  }
+  __syncthreads();
+}
+
+template <typename T, bool CLS, bool JAC>
 __global__ void __launch_bounds__(kTailThreads)
     k_vtail(TailDesc<T> td, const T *__restrict__ b_top, T *__restrict__ x_top, int nu) {
   extern __shared__ unsigned char smem_raw[];
@@ -444,8 +516,12 @@ __global__ void __launch_bounds__(kTailThreads)
     for (int p = threadIdx.x; p < n; p += kTailThreads) sx[p] = T(0);
     __syncthreads();
     for (int sw = 0; sw < nu; ++sw) {
-      tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 0);
-      tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 1);
+      if constexpr (JAC) {
+        tail_jsweep<T, CLS>(td, cls_lds, l, sx, sb);
+      } else {
+        tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 0);
+        tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 1);
+      }
     }
     const int ncx = td.nx[l + 1], ncy = td.ny[l + 1];
     T *sbc = sm + td.off[l + 1];
@@ -492,8 +568,12 @@ __global__ void __launch_bounds__(kTailThreads)
       sx[p] += prolong_value(sxc, ncx, 0, 0, p % nx, p / nx, ncx, ncy, td.pw[l], td.pa, td.pn);
     __syncthreads();
     for (int sw = 0; sw < nu; ++sw) {
-      tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 1);
-      tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 0);
+      if constexpr (JAC) {
+        tail_jsweep<T, CLS>(td, cls_lds, l, sx, sb);
+      } else {
+        tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 1);
+        tail_sweep<T, CLS>(td, cls_lds, l, sx, sb, 0);
+      }
     }
   }
   {
@@ -513,26 +593,42 @@ bool small_tiles(int nx, int ny) {
 
 namespace kern {
 
-template <typename T, int NPT, bool CLS, int NU>
-void vdown_t(const OpView<T> &D, const T *b, T *rc, hipStream_t st) {
+template <typename T, int NPT, bool CLS, int NU, bool JAC>
+void vdown_tj(const OpView<T> &D, const T *b, T *rc, hipStream_t st) {
   if (small_tiles(D.nx, D.ny)) {
     dim3 grid((D.nx + 31) / 32, (D.ny + 15) / 16);
-    k_vdown<T, NPT, CLS, NU, 32, 16><<<grid, kNT, 0, st>>>(D, b, rc);
+    k_vdown<T, NPT, CLS, NU, 32, 16, JAC><<<grid, kNT, 0, st>>>(D, b, rc);
   } else {
     dim3 grid((D.nx + 63) / 64, (D.ny + 31) / 32);
-    k_vdown<T, NPT, CLS, NU, 64, 32><<<grid, kNT, 0, st>>>(D, b, rc);
+    k_vdown<T, NPT, CLS, NU, 64, 32, JAC><<<grid, kNT, 0, st>>>(D, b, rc);
+  }
+}
+
+template <typename T, int NPT, bool CLS, int NU>
+void vdown_t(const OpView<T> &D, const T *b, T *rc, hipStream_t st) {
+  if (D.jw > T(0))
+    vdown_tj<T, NPT, CLS, NU, true>(D, b, rc, st);
+  else
+    vdown_tj<T, NPT, CLS, NU, false>(D, b, rc, st);
+}
+
+template <typename T, int NPT, bool CLS, int NU, bool JAC>
+void vup_tj(const OpView<T> &D, const T *b, const T *ec, T *x, hipStream_t st) {
+  if (small_tiles(D.nx, D.ny)) {
+    dim3 grid((D.nx + 31) / 32, (D.ny + 15) / 16);
+    k_vup<T, NPT, CLS, NU, 32, 16, JAC><<<grid, kNT, 0, st>>>(D, b, ec, x);
+  } else {
+    dim3 grid((D.nx + 63) / 64, (D.ny + 31) / 32);
+    k_vup<T, NPT, CLS, NU, 64, 32, JAC><<<grid, kNT, 0, st>>>(D, b, ec, x);
   }
 }
 
 template <typename T, int NPT, bool CLS, int NU>
 void vup_t(const OpView<T> &D, const T *b, const T *ec, T *x, hipStream_t st) {
-  if (small_tiles(D.nx, D.ny)) {
-    dim3 grid((D.nx + 31) / 32, (D.ny + 15) / 16);
-    k_vup<T, NPT, CLS, NU, 32, 16><<<grid, kNT, 0, st>>>(D, b, ec, x);
-  } else {
-    dim3 grid((D.nx + 63) / 64, (D.ny + 31) / 32);
-    k_vup<T, NPT, CLS, NU, 64, 32><<<grid, kNT, 0, st>>>(D, b, ec, x);
-  }
+  if (D.jw > T(0))
+    vup_tj<T, NPT, CLS, NU, true>(D, b, ec, x, st);
+  else
+    vup_tj<T, NPT, CLS, NU, false>(D, b, ec, x, st);
 }
 
 #define IRK_V_DISPATCH(FN, ...)                                                   \
@@ -602,12 +698,20 @@ size_t vtail_lds_bytes(const TailDesc<T> &td) {
   return n * sizeof(T);
 }
 
+template <typename T, bool JAC>
+void vtail_j(const TailDesc<T> &td, int nu, const T *b, T *x, hipStream_t st) {
+  if (td.cls[0] || td.nlev == 1)
+    k_vtail<T, true, JAC><<<1, kTailThreads, vtail_lds_bytes(td), st>>>(td, b, x, nu);
+  else
+    k_vtail<T, false, JAC><<<1, kTailThreads, vtail_lds_bytes(td), st>>>(td, b, x, nu);
+}
+
 template <typename T>
 void vtail(const TailDesc<T> &td, int nu, const T *b, T *x, hipStream_t st) {
-  if (td.cls[0] || td.nlev == 1)
-    k_vtail<T, true><<<1, kTailThreads, vtail_lds_bytes(td), st>>>(td, b, x, nu);
+  if (td.jw > T(0))
+    vtail_j<T, true>(td, nu, b, x, st);
   else
-    k_vtail<T, false><<<1, kTailThreads, vtail_lds_bytes(td), st>>>(td, b, x, nu);
+    vtail_j<T, false>(td, nu, b, x, st);
 }
 
 template void vdown<float>(const OpView<float> &, int, const float *, float *, hipStream_t);

@@ -45,7 +45,7 @@ class IRKSolver:
     def __init__(self, A, b, c, K, h_t, grid, precision="fp64", precond="LD", restart=40,
                  max_iter=200, nu_pre=2, nu_post=2, coarse_max=64, rtol=1e-8, true_resid=True,
                  reorth=0, side="right", M=None, interp="linear", graphs=None,
-                 coarse_ratio=None, device=None):
+                 coarse_ratio=None, smoother="rbgs", jacobi_omega=0.8, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("IRKSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = B.lib()
@@ -74,6 +74,8 @@ class IRKSolver:
             opt.graphs = 1 if graphs else 0
         if coarse_ratio is not None:
             opt.coarse_ratio = float(coarse_ratio)
+        opt.smoother = B.SMOOTHER[smoother]
+        opt.jacobi_omega = float(jacobi_omega)
         self.options = opt
         tab = B.Butcher(self.s, B.dptr(self.A), B.dptr(self._b), B.dptr(self._c))
         csr, keep = _csr_struct(*K)

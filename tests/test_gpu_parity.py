@@ -171,6 +171,79 @@ def test_vcycle_preconditioner_matches_oracle(dev, problem, nx, ny, precision):
     S.close()
 
 
+@pytest.mark.parametrize("problem,nx,ny,precision", [
+    ("heat", 200, 136, "mixed"), ("heat", 200, 136, "fp64"), ("heat", 512, 512, "mixed"),
+    ("heat", 512, 512, "fp64"), ("heat", 640, 416, "mixed"), ("heat", 1024, 1024, "mixed"),
+    ("dg", 128, 128, "fp64"), ("dg", 256, 256, "mixed"), ("kappa", 128, 128, "fp64"),
+    ("kappa", 192, 192, "mixed")])
+def test_vcycle_jacobi_matches_oracle(dev, problem, nx, ny, precision):
+    """The same with damped Jacobi smoothing (omega 0.8, two sweeps before and
+    after the coarse correction) against the oracle's Jacobi V-cycle."""
+    from oracle.amg import apply_vcycle_preconditioner
+    say("case vcycle jacobi vs oracle", problem, nx, ny, precision)
+    s, h = 3, 1e-3
+    A, b, c = tableaux.tableau("radau_iia", s)
+    if problem == "heat":
+        Kp, Ko = problems.heat(nx, ny=ny), heat_K(nx, ny=ny)
+    elif problem == "dg":
+        Kp, Ko = problems.double_glazing(nx, 0.005)[:3], double_glazing(nx, 0.005)[0]
+    else:
+        kn = np.exp(workloads.gaussian_random_field(nx + 2, seed=3))
+        Kp, Ko = problems.kappa_diffusion(kn), kappa_diffusion_K(kn)
+    S = Solver(A, b, c, Kp, h, (nx, ny), precision=precision, smoother="jacobi",
+               jacobi_omega=0.8, device=dev)
+    say("  hierarchy", S.info())
+    v = np.random.default_rng(12).standard_normal(s * nx * ny)
+    z = S.apply_preconditioner(T(v, dev)).cpu().numpy()
+    Ao = oracle_tableau("radau_iia", s)[0]
+    ref = apply_vcycle_preconditioner(coefficient_matrix(Ao, "LD"), Ko, h, v.reshape(s, -1),
+                                      nx, ny, nu=2, coarse_max=64,
+                                      coarse_ratio=S.options.coarse_ratio, smoother="jacobi",
+                                      omega=0.8).ravel()
+    err = rel(z, ref)
+    say("  rel err", err)
+    assert err < (1e-11 if precision == "fp64" else 2e-5)
+    S.close()
+
+
+@pytest.mark.parametrize("problem,precision", [("heat", "mixed"), ("heat", "fp64"),
+                                               ("dg", "mixed")])
+def test_steps_with_jacobi_smoothing_match_oracle(dev, problem, precision):
+    """Whole steps with damped Jacobi V-cycles reach the oracle's exact steps:
+    heat 256^2 Gauss-Legendre 7 (h_t 1e-3, the 8-mode field) and double
+    glazing 256^2 Radau IIA 5 (h_t 5e-3, from zero), five steps each."""
+    say("case steps jacobi", problem, precision)
+    n, steps = 256, 5
+    if problem == "heat":
+        fam, s, h = "gauss", 7, 1e-3
+        A, b, c = tableaux.tableau(fam, s)
+        S = Solver(A, b, c, problems.heat(n), h, (n, n), precision=precision, rtol=1e-10,
+                   smoother="jacobi", device=dev)
+        u0 = workloads.fourier_modes(n, seed=0)
+        Ao, bo, _ = oracle_tableau(fam, s)
+        ref = run_steps(HeatDSTStepper(Ao, bo, n, h), u0, steps)
+    else:
+        fam, s, h = "radau_iia", 5, 5e-3
+        A, b, c = tableaux.tableau(fam, s)
+        ip, ix, d, g = problems.double_glazing(n, 0.005)
+        S = Solver(A, b, c, (ip, ix, d), h, (n, n), precision=precision, rtol=1e-10,
+                   smoother="jacobi", device=dev)
+        S.set_source(g)
+        u0 = np.zeros(n * n)
+        Ko, go = double_glazing(n, 0.005)
+        Ao, bo, _ = oracle_tableau(fam, s)
+        ref = run_steps(EigenStepper(Ao, bo, Ko, h, go), u0, steps)
+    u = T(u0, dev)
+    its = []
+    for _ in range(steps):
+        u = S.step(u)
+        its.append(S.last_stats.iters)
+    err = rel(u.cpu().numpy(), ref)
+    say("  iterations %s, rel err %.2e" % (its, err))
+    assert err <= 1e-8
+    S.close()
+
+
 # ------------------------------------------------------------------ steps
 def test_step_c1_gl2_32(dev):
     """32x32 heat, sin(pi x) sin(pi y), GL2, h = 0.01, 10 steps, rtol 1e-10."""

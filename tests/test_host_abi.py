@@ -47,6 +47,7 @@ def test_default_options():
     assert o.interp == B.IRK_INTERP_LINEAR
     assert o.graphs == 0
     assert o.coarse_ratio == 2.0
+    assert o.smoother == B.SMOOTHER["rbgs"] and o.jacobi_omega == 0.8
 
 
 def test_status_strings():
@@ -116,6 +117,14 @@ def test_setup_validation_before_any_device_work():
     opt.graphs = 2
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
     assert st == B.IRK_E_INVALID and "graphs" in msg
+    opt = B.default_options()
+    opt.smoother = 2
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
+    assert st == B.IRK_E_INVALID and "smoother" in msg
+    opt = B.default_options()
+    opt.smoother, opt.jacobi_omega = B.SMOOTHER["jacobi"], 1.5
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
+    assert st == B.IRK_E_INVALID and "jacobi_omega" in msg
     opt = B.default_options()
     opt.side, opt.precision = B.IRK_LEFT, B.IRK_MIXED
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
