@@ -43,13 +43,31 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # FETCH_SIZE / WRITE_SIZE per dispatch, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0; see profiles/spmm_update_heat2048_gl7_hbm_counters.md), as a
 # function of the Krylov index j.  Valid only for the kernel source it was
-# taken on: reported as null once that file changes.
+# taken on (the SpMM section of the source file, from the first marker line
+# to the second): reported as null once that text changes.
 SPMM_UPDATE_TRAFFIC = {
     "source": os.path.join("paper_2010_11377_amd", "csrc", "kernels.hip"),
-    "sha256": "0a7a77cd9bbe16f4d641dba2d833683c862e479eb609eef97c4847254dfb9739",
+    "begin": "// Kronecker SpMM with fused Gram-Schmidt",
+    "end": "// Second Gram-Schmidt pass on the new column",
+    "sha256": "d07ff6a517456b16fa30672d8d486aed43968849dc4d57892e7233420dad51a1",
     "fetch_kib": (1.9999 * 58533.7, 1.9999 * 121253.6),  # a + b (j + 1), scaled
     "write_kib": 229950.8,
 }
+
+
+def spmm_source_sha():
+    """SHA-256 of the SpMM section of the kernel source (None if unreadable)."""
+    import hashlib
+    rec = SPMM_UPDATE_TRAFFIC
+    try:
+        with open(os.path.join(ROOT, rec["source"]), encoding="utf-8") as f:
+            text = f.read()
+    except OSError:
+        return None
+    i, j = text.find(rec["begin"]), text.find(rec["end"])
+    if i < 0 or j <= i:
+        return None
+    return hashlib.sha256(text[i:j].encode("utf-8")).hexdigest()
 
 
 def spmm_update_traffic(iters_per_step):
@@ -58,11 +76,7 @@ def spmm_update_traffic(iters_per_step):
     source differs from the one measured."""
     import hashlib
     rec = SPMM_UPDATE_TRAFFIC
-    try:
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
-                return None
-    except OSError:
+    if spmm_source_sha() != rec["sha256"]:
         return None
     js = [j for it in iters_per_step for j in range(it)]
     if not js:
