@@ -114,6 +114,10 @@ def parse():
                     help="skip the oracle check of the double-glazing run")
     ap.add_argument("--dg-only", action="store_true",
                     help="run only the double-glazing workload and print its record (profiling)")
+    ap.add_argument("--configs", action="store_true",
+                    help="only time the smaller configurations (32^2 GL2, 512^2 Radau IIA 3 in both "
+                         "forms, the 256^2 kappa-diffusion adjoint gradient), each checked against "
+                         "the oracle, and print their table as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling hardware byte counters)")
@@ -236,6 +240,96 @@ def double_glazing_run(args, torch, np, dev, smoother="rbgs", ref=None):
     return out, ref
 
 
+def small_configs(torch, np, dev):
+    """The smaller configurations, each timed after one warm-up pass and
+    checked against the oracle on the same input.
+
+    * heat 32^2, u0 = sin(pi x) sin(pi y), Gauss-Legendre 2, h_t = 0.01,
+      10 steps, FP64, FGMRES to 1e-10;
+    * heat 512^2, 8 random sine modes (seed 0), Radau IIA 3, h_t = 1e-3,
+      50 steps, FP64 and mixed, FGMRES to 1e-9 per step;
+    * kappa-diffusion 256^2, kappa = exp(g) (Gaussian random field, seed 3),
+      Radau IIA 3, h_t = 2e-3, 20 steps, J = 1/2 ||u_T - u_target||^2 and
+      dJ/dkappa (nodal) by the discrete adjoint, FP64, FGMRES to 1e-12."""
+    from oracle import adjoint as oracle_adjoint
+    from oracle.operators import heat_K as oracle_heat
+    from oracle.step import DirectStepper, HeatDSTStepper, run_steps
+    from oracle.tableau import tableau as oracle_tableau
+    from paper_2010_11377_amd import problems, tableaux, workloads
+    from paper_2010_11377_amd.autograd import IRKDiffusionFn
+    from paper_2010_11377_amd.solver import IRKSolver
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def heat_case(name, n, fam, s, h, steps, precision, rtol, u0, ref):
+        A, b, c = tableaux.tableau(fam, s)
+        S = IRKSolver(A, b, c, problems.heat(n), h, (n, n), precision=precision, rtol=rtol,
+                      device=dev)
+        u0t = torch.tensor(u0, dtype=torch.float64, device=dev)
+        u, secs, iters, _ = timed_run(S, u0t, steps, 1, torch)
+        S.close()
+        err = rel(u.cpu().numpy(), ref)
+        log("[bench] %s %s: %d steps in %.4fs, iters %s, rel err %.2e" % (
+            name, precision, steps, secs, iters[:5], err))
+        return {"steps_per_s": round(steps / secs, 2), "ms_per_step": round(1e3 * secs / steps, 3),
+                "iters_per_step_mean": round(float(np.mean(iters)), 2),
+                "rel_err_vs_oracle": err}
+
+    out = {}
+    n, h, steps = 32, 0.01, 10
+    u0 = workloads.sine_mode(n)
+    Ao, bo, _ = oracle_tableau("gauss", 2)
+    ref = run_steps(DirectStepper(Ao, bo, oracle_heat(n), h), u0, steps)
+    out["heat_32x32_gl2_ht1e-2_10steps"] = {
+        "fp64": heat_case("32^2 GL2", n, "gauss", 2, h, steps, "fp64", 1e-10, u0, ref)}
+    n, h, steps = 512, 1e-3, 50
+    u0 = workloads.fourier_modes(n, seed=0)
+    Ao, bo, _ = oracle_tableau("radau_iia", 3)
+    ref = run_steps(HeatDSTStepper(Ao, bo, n, h), u0, steps)
+    out["heat_512x512_radau3_ht1e-3_50steps"] = {
+        p: heat_case("512^2 RIIA3", n, "radau_iia", 3, h, steps, p, 1e-9, u0, ref)
+        for p in ("fp64", "mixed")}
+
+    n, h, steps = 256, 2e-3, 20
+    hx = 1.0 / (n + 1)
+    kn = np.exp(workloads.gaussian_random_field(n + 2, seed=3))
+    u0 = workloads.fourier_modes(n, seed=2)
+    A, b, c = tableaux.tableau("radau_iia", 3)
+    S = IRKSolver(A, b, c, problems.kappa_diffusion(kn), h, (n, n), rtol=1e-12, device=dev)
+    Ao, bo, _ = oracle_tableau("radau_iia", 3)
+    u_tgt_np = oracle_adjoint.forward(Ao, bo, np.ones((n + 2, n + 2)), h, u0, steps)[0]
+    u0t = torch.tensor(u0, dtype=torch.float64, device=dev)
+    u_tgt = torch.tensor(u_tgt_np, dtype=torch.float64, device=dev)
+
+    def grad_once():
+        kt = torch.tensor(kn, dtype=torch.float64, device=dev, requires_grad=True)
+        uT = IRKDiffusionFn.apply(kt, u0t, S, steps, hx)
+        J = 0.5 * torch.sum((uT - u_tgt) ** 2)
+        J.backward()
+        return J.detach(), kt.grad
+
+    grad_once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = grad_once()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    S.close()
+    t0 = time.perf_counter()
+    J_ref, g_ref = oracle_adjoint.gradient(Ao, bo, kn, h, u0, steps, u_tgt_np)
+    t_oracle = time.perf_counter() - t0
+    g = g.cpu().numpy()
+    rec = {"gradients_per_s": round(1.0 / secs, 3), "ms_per_gradient": round(1e3 * secs, 2),
+           "J_rel_err_vs_oracle": abs(float(J) - J_ref) / J_ref,
+           "grad_rel_err_vs_oracle": rel(g, g_ref),
+           "oracle_s": round(t_oracle, 2)}
+    log("[bench] adjoint 256^2: gradient in %.4fs, grad rel err %.2e (oracle %.1fs)" % (
+        secs, rec["grad_rel_err_vs_oracle"], t_oracle))
+    out["kappa_diffusion_256x256_radau3_ht2e-3_20steps_adjoint"] = {"fp64": rec}
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -255,6 +349,10 @@ def main():
     dev = torch.device("cuda", 0)
     if args.dg_only:
         print(json.dumps(double_glazing_run(args, torch, np, dev, args.smoother)[0]), flush=True)
+        return
+    if args.configs:
+        print(json.dumps({"configs": small_configs(torch, np, dev), "n_gpus": 1,
+                          "data": "synthetic"}), flush=True)
         return
     A, b, c = tableaux.tableau("gauss", s)
     Kop = problems.heat(n)
