@@ -144,6 +144,10 @@ typedef struct {
                       IRK_SMOOTH_JACOBI: damped Jacobi x += jacobi_omega
                       D^-1 (b - D x), every node from the old values. */
   double jacobi_omega; /* Jacobi damping weight in (0, 1] (default 0.8) */
+  int fuse_levels; /* 1: two adjacent intermediate nine-point levels share one
+                      launch per direction where the grid allows it (FP32
+                      V-cycles, nu = 2, red-black smoothing), the default.
+                      0: one launch per level.  The results are the same. */
 } irk_options;
 
 typedef struct {
@@ -157,7 +161,8 @@ typedef struct {
 /* Fill *opt with the defaults: IRK_FP64, IRK_PREC_LD, restart 40,
  * max_iter 200, nu_pre = nu_post = 2, coarse_max 64, vcycles 1,
  * true_resid 1, reorth 0, rtol 1e-8, side IRK_RIGHT, interp IRK_INTERP_LINEAR,
- * graphs 0, coarse_ratio 2, smoother IRK_SMOOTH_RBGS, jacobi_omega 0.8. */
+ * graphs 0, coarse_ratio 2, smoother IRK_SMOOTH_RBGS, jacobi_omega 0.8,
+ * fuse_levels 1. */
 void irk_default_options(irk_options *opt);
 
 /* LDU factorisation without pivoting, A = L diag(d) U (Sec. 4.1), host only.

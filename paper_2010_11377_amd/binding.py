@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("side", ctypes.c_int),
                 ("interp", ctypes.c_int), ("graphs", ctypes.c_int),
                 ("coarse_ratio", ctypes.c_double), ("smoother", ctypes.c_int),
-                ("jacobi_omega", ctypes.c_double)]
+                ("jacobi_omega", ctypes.c_double), ("fuse_levels", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

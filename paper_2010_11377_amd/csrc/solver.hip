@@ -639,6 +639,21 @@ bool ws9_usable(const DevOp<T> &D, int nu) {
   return linear_p(D) && irk::kern::ws9_ok<T>(D.view(), nu);
 }
 
+// Levels l and l + 1 (both intermediate: the finest level and the tail have
+// kernels of their own) run as one pair in each direction.
+template <typename T>
+bool pair_ok(const irk_solver *S, int i, int l) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (!S->opt.fuse_levels || jacobi(S) || l < 1) return false;
+    const DevOp<float> &Df = Dops<float>(S)[i][l];
+    const DevOp<float> &Dc = Dops<float>(S)[i][l + 1];
+    return linear_p(Df) && linear_p(Dc) &&
+           irk::kern::s9pair_ok(Df.view(), Dc.view(), S->opt.nu_pre);
+  } else {
+    return false;
+  }
+}
+
 template <typename T>
 void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
   if (D.jw > T(0)) return irk::kern::vdown<T>(D.view(), nu, b, rc, st);  // damped Jacobi
@@ -688,6 +703,18 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   for (int l = finest_down_done ? 1 : 0; l < lt; ++l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
+    if (l > 0 && l + 1 < lt && pair_ok<T>(S, i, l)) {
+      // levels l and l + 1 in one launch
+      const DevOp<T> &Dc = Dops<T>(S)[i][l + 1];
+      const size_t nc = (size_t)Dc.nx * Dc.ny;
+      ProfTok t = prof_begin(S, IRK_KC_VMID_DOWN, (double)(n + nc) * es * 1.25);
+      if constexpr (std::is_same_v<T, float>)
+        irk::kern::s9down2(D.view(), D.classes, Dc.view(), Dc.classes, bl(l), lev_p<T>(S, l),
+                           lev_b<T>(S, l + 1), lev_p<T>(S, l + 1), lev_b<T>(S, l + 2), st);
+      prof_end(S, t);
+      ++l;
+      continue;
+    }
     if (l == 0 && S->fine_mode && !jacobi(S)) {
       // b and K per node (read) in, the coarse residual and the pre-smoothed x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
@@ -741,6 +768,18 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
   for (int l = lt - 1; l >= 0; --l) {
     const DevOp<T> &D = Dops<T>(S)[i][l];
     const size_t n = (size_t)D.nx * D.ny;
+    if (l > 1 && pair_ok<T>(S, i, l - 1)) {
+      // levels l and l - 1 in one launch: l's x stays on chip
+      const DevOp<T> &Df = Dops<T>(S)[i][l - 1];
+      const size_t nf = (size_t)Df.nx * Df.ny;
+      ProfTok t = prof_begin(S, IRK_KC_VMID_UP, (double)(n + nf) * es * 2.25);
+      if constexpr (std::is_same_v<T, float>)
+        irk::kern::s9up2(Df.view(), Df.classes, D.view(), D.classes, bl(l - 1), lev_p<T>(S, l - 1),
+                         bl(l), lev_p<T>(S, l), l == E ? zero : lev_x<T>(S, l + 1), xl(l - 1), st);
+      prof_end(S, t);
+      --l;
+      continue;
+    }
     if (l == 0 && S->fine_mode && !jacobi(S)) {
       // b, the pre-smoothed x, K per node and the coarse correction in, x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
@@ -1237,6 +1276,7 @@ bool valid_options(const irk_options &o, std::string &err) {
     return err = "smoother must be IRK_SMOOTH_RBGS or IRK_SMOOTH_JACOBI", false;
   if (o.smoother == IRK_SMOOTH_JACOBI && !(o.jacobi_omega > 0.0 && o.jacobi_omega <= 1.0))
     return err = "jacobi_omega must be in (0, 1]", false;
+  if (o.fuse_levels != 0 && o.fuse_levels != 1) return err = "fuse_levels must be 0 or 1", false;
   return true;
 }
 
@@ -1401,6 +1441,7 @@ void irk_default_options(irk_options *o) {
   o->coarse_ratio = 2.0;
   o->smoother = IRK_SMOOTH_RBGS;
   o->jacobi_omega = 0.8;
+  o->fuse_levels = 1;
 }
 
 irk_status irk_ldu(int s, const double *A, double *L, double *d, double *U) {

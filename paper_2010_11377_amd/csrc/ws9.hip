@@ -510,6 +510,332 @@ dim3 grid9(int nx, int ny) {
   return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kW9 - 1) / (G::TY * kW9));
 }
 
+// ===========================================================================
+// Two adjacent levels in one launch (nu = 2), the fine level F and its coarse
+// level C = F + 1, both nine-point with constant coefficients per class.
+//
+// Down: a workgroup owns a block of C of kD2TYC x kD2TXC nodes.  Its kD2W
+// waves pre-smooth F on overlapping tiles that cover the 2 x 2 cells of that
+// block widened by the halo H of C, restrict the residual into LDS, and store
+// the pre-smoothed x of the F nodes inside the block; then wave 0 pre-smooths
+// C on the LDS right-hand side (one register tile of 16 rows, 60 of its 128
+// columns filled: the outputs lie at least H nodes inside the filled part, so
+// the unfilled columns cannot reach them), stores C's x and b, and restricts
+// C's residual to the next level.
+//
+// Up: a workgroup owns kU2W tiles of F of the single-level up pass (the same
+// placement).  Its two waves first correct and post-smooth C on two register
+// tiles of 16 rows that together cover every C node those tiles read, H nodes
+// deeper, and park the needed part in LDS; then every wave post-smooths its
+// tile of F with its C values taken from LDS.
+//
+// Row classes stay compile-time: a boundary row of C lies at a fixed tile row
+// in the first and last workgroup rows and otherwise only at a tile's outer
+// edge row, which is never relaxed.  Column classes are chosen per lane from
+// the global column.  Each node goes through the same arithmetic as in the
+// one-level passes, so the results are the same bits.
+constexpr int kD2W = 4, kD2TYC = 8, kD2TXC = 52;
+constexpr int kD2BC = kD2TXC + 8;  // coarse columns filled from LDS (outputs + 2 H)
+constexpr int kU2W = 2;
+constexpr int kU2XR = 4 * kU2W + 7;  // coarse rows the fine tiles read
+
+__device__ __forceinline__ bool interior_w(int X0, int Y0, int w, int R, int nx, int ny) {
+  return X0 >= 1 && Y0 >= 1 && X0 + w <= nx - 1 && Y0 + R <= ny - 1;
+}
+
+// Coarse right-hand sides of the 2 x 2 cells of a pre-smoothed tile's output
+// rows (sums of the residual; zero outside the grid), one per lane and row pair.
+template <typename T, bool BOUND, int R, int H, int TY, int YB>
+__device__ __forceinline__ void s9_sums(const Ctx<T, BOUND, R, H, TY, YB> &cx, const T9<T, R> &t,
+                                        T (&cs)[TY / 2]) {
+  const bool inx = cx.lane_in();
+#pragma unroll
+  for (int r = H, k = 0; r < H + TY; r += 2, ++k) {
+    T sum = T(0);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int rr = r + d;
+      if (!cx.row_in(rr)) continue;
+      const Co<T> ca = cx.a(rr), cb = cx.b(rr);
+      const T ra = t.ba[rr] - ca.c[4] * t.xa[rr] - offdiag_a<T, R>(ca, t, rr);
+      const T rb = t.bb[rr] - cb.c[4] * t.xb[rr] - offdiag_b<T, R>(cb, t, rr);
+      sum += ra + rb;
+    }
+    cs[k] = inx ? sum : T(0);
+  }
+}
+
+template <typename T, bool BOUND, int R, int H, int TY, int YB>
+__device__ __forceinline__ void s9_pre_sums(const S9Op<T> &o, const Place &p, const MidCo<T> &m,
+                                            T9<T, R> &t, T (&cs)[TY / 2]) {
+  const Ctx<T, BOUND, R, H, TY, YB> cx{o, p, m};
+  s9_pre<T, BOUND, R, H, TY, YB, 2>(cx, t);
+  s9_sums<T, BOUND, R, H, TY, YB>(cx, t, cs);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kD2W)
+    k_s9down2(S9Op<T> of, S9Op<T> oc, const T *__restrict__ bin, T *__restrict__ xpre_f,
+              T *__restrict__ b_c, T *__restrict__ xpre_c, T *__restrict__ rcc) {
+  using V = typename P9<T>::V;
+  constexpr int TY = 8, H = 4, HX = 4, R = 16;
+  static_assert(2 * (kD2TYC + 2 * H) == kD2W * TY, "the fine tiles cover the coarse region");
+  __shared__ T bc[kD2TYC + 2 * H][kD2BC];
+  const int ncx = of.nx / 2, ncy = of.ny / 2;
+  const Tile2 tile = xcd_tile();
+  const int OXn = tile.x * kD2TXC;  // first coarse column this workgroup writes
+  const int OXc = min(OXn, ncx - kD2TXC), OYc = tile.y * kD2TYC;
+  const int Xc0 = OXc - H, Yc0 = OYc - H;  // origin of the coarse region
+  const int wave = threadIdx.x >> 6, lane = l9();
+
+  // ---- F: wave w pre-smooths rows OYf .. OYf + TY - 1 (halo H)
+  {
+    const int OYf = 2 * Yc0 + TY * wave;
+    T cs[TY / 2];
+#pragma unroll
+    for (int k = 0; k < TY / 2; ++k) cs[k] = T(0);
+    if (OYf >= 0 && OYf < of.ny) {
+      Place p;
+      p.X0 = 2 * Xc0 - HX;
+      p.Y0 = OYf - H;
+      p.OXn = 2 * OXn;
+      p.OYn = OYf;
+      p.lo = HX / 2;
+      p.hi = 64 - HX / 2;
+      p.top = OYf == 0;
+      p.bot = OYf == of.ny - TY;
+      p.fcol = p.X0 + 2 * lane == 0;
+      p.lcol = p.X0 + 2 * lane + 1 == of.nx - 1;
+      T9<T, R> t;
+      s9_load<T, R>(bin, t.ba, t.bb, p.X0, p.Y0, of.nx, of.ny);
+      if (interior_w(p.X0, p.Y0, 128, R, of.nx, of.ny)) {
+        s9_pre_sums<T, false, R, H, TY, 0>(of, p, MidCo<T>{}, t, cs);
+      } else {
+        const MidCo<T> m = mid_coefs(of, p);
+        if (p.top && p.bot)
+          s9_pre_sums<T, true, R, H, TY, 3>(of, p, m, t, cs);
+        else if (p.top)
+          s9_pre_sums<T, true, R, H, TY, 1>(of, p, m, t, cs);
+        else if (p.bot)
+          s9_pre_sums<T, true, R, H, TY, 2>(of, p, m, t, cs);
+        else
+          s9_pre_sums<T, true, R, H, TY, 0>(of, p, m, t, cs);
+      }
+      // the pre-smoothed x of the fine nodes of this workgroup's coarse block
+      const int gxa = p.X0 + 2 * lane;
+      if (OYf >= 2 * OYc && OYf < 2 * (OYc + kD2TYC) && gxa >= 2 * OXn &&
+          gxa < 2 * (OXc + kD2TXC) && gxa < of.nx) {
+#pragma unroll
+        for (int r = H; r < H + TY; ++r) {
+          V v;
+          v.x = t.xa[r];
+          v.y = t.xb[r];
+          *reinterpret_cast<V *>(xpre_f + (size_t)(p.Y0 + r) * of.nx + gxa) = v;
+        }
+      }
+    }
+    const int c = lane - HX / 2;
+    if (c >= 0 && c < kD2BC) {
+#pragma unroll
+      for (int k = 0; k < TY / 2; ++k) bc[TY / 2 * wave + k][c] = cs[k];
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+
+  // ---- C: one tile of R = 16 rows on the coarse region
+  Place p;
+  p.X0 = Xc0;
+  p.Y0 = Yc0;
+  p.OXn = OXn;
+  p.OYn = OYc;
+  p.lo = H / 2;
+  p.hi = H / 2 + kD2TXC / 2;
+  p.top = OYc == 0;
+  p.bot = OYc == ncy - kD2TYC;
+  p.fcol = p.X0 + 2 * lane == 0;
+  p.lcol = p.X0 + 2 * lane + 1 == ncx - 1;
+  T9<T, R> t;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T a = T(0), b = T(0);
+    if (lane < kD2BC / 2) {
+      a = bc[r][2 * lane];
+      b = bc[r][2 * lane + 1];
+    }
+    t.ba[r] = a;
+    t.bb[r] = b;
+  }
+  if (interior_w(p.X0, p.Y0, kD2BC, R, ncx, ncy)) {
+    s9_down_tile<T, false, R, H, TY, 0, 2>(oc, p, MidCo<T>{}, t, rcc);
+  } else {
+    const MidCo<T> m = mid_coefs(oc, p);
+    if (p.top && p.bot)
+      s9_down_tile<T, true, R, H, TY, 3, 2>(oc, p, m, t, rcc);
+    else if (p.top)
+      s9_down_tile<T, true, R, H, TY, 1, 2>(oc, p, m, t, rcc);
+    else if (p.bot)
+      s9_down_tile<T, true, R, H, TY, 2, 2>(oc, p, m, t, rcc);
+    else
+      s9_down_tile<T, true, R, H, TY, 0, 2>(oc, p, m, t, rcc);
+  }
+  const int gxa = p.X0 + 2 * lane;
+  if (lane >= p.lo && lane < p.hi && gxa >= OXn && gxa < ncx) {
+#pragma unroll
+    for (int r = H; r < H + TY; ++r) {
+      const size_t q = (size_t)(p.Y0 + r) * ncx + gxa;
+      V v;
+      v.x = t.xa[r];
+      v.y = t.xb[r];
+      *reinterpret_cast<V *>(xpre_c + q) = v;
+      v.x = t.ba[r];
+      v.y = t.bb[r];
+      *reinterpret_cast<V *>(b_c + q) = v;
+    }
+  }
+}
+
+template <typename T, bool BOUND, int HC, int YB>
+__device__ __forceinline__ void s9_up_coarse(const S9Op<T> &o, const Place &p, T9<T, 16> &t,
+                                             const T (&cr)[11]) {
+  const MidCo<T> m = BOUND ? mid_coefs(o, p) : MidCo<T>{};
+  s9_up_tile<T, BOUND, 16, HC, 8, YB, 2>(o, p, m, t, cr);
+}
+
+// One of the two coarse tiles of the up pair: rows Y0 .. Y0 + 15, where the
+// grid's first row can only sit at tile row HC and its last at HC + 7.
+template <typename T, int HC>
+__device__ __forceinline__ void s9_up_coarse_any(const S9Op<T> &o, const Place &p, T9<T, 16> &t,
+                                                 const T (&cr)[11], bool interior) {
+  if (interior)
+    s9_up_coarse<T, false, HC, 0>(o, p, t, cr);
+  else if (p.top && p.bot)
+    s9_up_coarse<T, true, HC, 3>(o, p, t, cr);
+  else if (p.top)
+    s9_up_coarse<T, true, HC, 1>(o, p, t, cr);
+  else if (p.bot)
+    s9_up_coarse<T, true, HC, 2>(o, p, t, cr);
+  else
+    s9_up_coarse<T, true, HC, 0>(o, p, t, cr);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kU2W)
+    k_s9up2(S9Op<T> of, S9Op<T> oc, const T *__restrict__ bf, const T *__restrict__ xpre_f,
+            const T *__restrict__ b_c, const T *__restrict__ xpre_c, const T *__restrict__ ecc,
+            T *__restrict__ xf) {
+  using G = G9<2, 8, true>;
+  using V = typename P9<T>::V;
+  constexpr int H = G::H, R = G::R, TY = G::TY;
+  static_assert(kU2W == 2 && kU2XR == 15, "two coarse tiles of 16 rows cover the rows read");
+  __shared__ T xs[kU2XR][64];
+  const int ncx = of.nx / 2, ncy = of.ny / 2;
+  const Tile2 tile = xcd_tile();
+  const int OXn = tile.x * G::TXO, OX = min(OXn, of.nx - G::TXO);
+  const int OY = tile.y * TY * kU2W;
+  const int X0f = OX - G::HX;
+  const int Ic = X0f >> 1;              // coarse column of lane 0 in the fine tiles
+  const int Jlo = ((OY - H) >> 1) - 1;  // first coarse row the fine tiles read
+  const int wave = threadIdx.x >> 6, lane = l9();
+
+  // the fine tile's inputs first, so that their latency overlaps the coarse work
+  Place p;
+  p.OXn = OXn;
+  p.OYn = OY + TY * wave;
+  p.X0 = X0f;
+  p.Y0 = p.OYn - H;
+  p.lo = G::HX / 2;
+  p.hi = 64 - G::HX / 2;
+  p.top = p.OYn == 0;
+  p.bot = p.OYn == of.ny - TY;
+  p.fcol = OX == 0 && lane == G::HX / 2;
+  p.lcol = OX == of.nx - G::TXO && lane == 63 - G::HX / 2;
+  T9<T, R> t;
+  s9_load<T, R>(bf, t.ba, t.bb, p.X0, p.Y0, of.nx, of.ny);
+  s9_load<T, R>(xpre_f, t.xa, t.xb, p.X0, p.Y0, of.nx, of.ny);
+
+  // ---- C: the rows read are Jlo .. Jlo + 14; wave 0 corrects and
+  // post-smooths coarse rows Y0c .. Y0c + 15 (valid 4 .. 11), wave 1 rows
+  // Y0c + 8 .. Y0c + 23 (valid 12 .. 19), with Y0c = Jlo - 5.  The correction
+  // leaves a tile's outermost columns without their outer coarse neighbour,
+  // so the columns read lie H + 1 inside the tile.
+  {
+    const int X0c = (Ic - H - 1) & ~1, Y0c = (Jlo - H) & ~1;
+    Place pc;
+    pc.X0 = X0c;
+    pc.Y0 = Y0c + 8 * wave;
+    pc.OXn = pc.OYn = 0;
+    pc.lo = 0;
+    pc.hi = 64;
+    pc.top = OY == 0;
+    pc.bot = OY == of.ny - TY * kU2W;
+    pc.fcol = X0c + 2 * lane == 0;
+    pc.lcol = X0c + 2 * lane + 1 == ncx - 1;
+    T9<T, 16> tc;
+    s9_load<T, 16>(b_c, tc.ba, tc.bb, pc.X0, pc.Y0, ncx, ncy);
+    s9_load<T, 16>(xpre_c, tc.xa, tc.xb, pc.X0, pc.Y0, ncx, ncy);
+    T cr[11];
+    {
+      const int ncx2 = ncx / 2, ncy2 = ncy / 2;
+      const int I = (X0c >> 1) + lane;
+#pragma unroll
+      for (int q = 0; q < 11; ++q) {
+        const int J = (pc.Y0 >> 1) - 1 + q;
+        cr[q] = (I >= 0 && I < ncx2 && J >= 0 && J < ncy2) ? ecc[(size_t)J * ncx2 + I] : T(0);
+      }
+    }
+    const bool interior = interior_w(X0c, Y0c, 2 * 40, 24, ncx, ncy);
+    // the grid's first row sits at row 8 of the first tile (row 0 of the
+    // second, its never-relaxed edge); the last at row 15 of the first tile
+    // (its edge) and row 7 of the second
+    if (wave == 0)
+      s9_up_coarse_any<T, 8>(oc, pc, tc, cr, interior);
+    else
+      s9_up_coarse_any<T, 0>(oc, pc, tc, cr, interior);
+    // park rows 4 .. 11 of the tile that are read, columns Ic .. Ic + 63
+    const int dc = Ic - X0c;
+    const int ca = 2 * lane - dc, cb = ca + 1;
+    const int q0 = pc.Y0 - Jlo;  // row of tile row 0 in xs
+#pragma unroll
+    for (int r = 4; r < 12; ++r) {
+      const int q = q0 + r;
+      if (q >= 0 && q < kU2XR) {
+        if (ca >= 0 && ca < 64) xs[q][ca] = tc.xa[r];
+        if (cb >= 0 && cb < 64) xs[q][cb] = tc.xb[r];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- F: the single-level up tile of wave w, C values from LDS
+  T cr[R / 2 + 3];
+#pragma unroll
+  for (int q = 0; q < R / 2 + 3; ++q) cr[q] = xs[TY / 2 * wave + q][lane];
+  if (!boundary_tile(p, R, of.nx, of.ny)) {
+    s9_up_tile<T, false, R, H, TY, 0, 2>(of, p, MidCo<T>{}, t, cr);
+  } else {
+    const MidCo<T> m = mid_coefs(of, p);
+    if (p.top && p.bot)
+      s9_up_tile<T, true, R, H, TY, 3, 2>(of, p, m, t, cr);
+    else if (p.top)
+      s9_up_tile<T, true, R, H, TY, 1, 2>(of, p, m, t, cr);
+    else if (p.bot)
+      s9_up_tile<T, true, R, H, TY, 2, 2>(of, p, m, t, cr);
+    else
+      s9_up_tile<T, true, R, H, TY, 0, 2>(of, p, m, t, cr);
+  }
+  const int gxa = p.X0 + 2 * lane;
+  if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < of.nx) {
+#pragma unroll
+    for (int r = H; r < R - H; ++r) {
+      V v;
+      v.x = t.xa[r];
+      v.y = t.xb[r];
+      *reinterpret_cast<V *>(xf + (size_t)(p.Y0 + r) * of.nx + gxa) = v;
+    }
+  }
+}
+
 // Grid shapes the tiling takes: even dimensions, nx >= 128, ny a multiple of
 // TY, and the grid's last column not inside the halo of the second-to-last
 // tile column (nx mod TXO zero or beyond the halo width H).
@@ -569,6 +895,33 @@ template void s9down<double>(const OpView<double> &, const double *, int, const 
                              double *, double *, hipStream_t);
 template void s9up<float>(const OpView<float> &, const float *, int, const float *, const float *,
                           const float *, float *, hipStream_t);
+
+// Pairs: nu = 2, both levels on the register tiling, C = F / 2 exactly, F's
+// height a multiple of 16 (C's a multiple of the coarse block height) and
+// C's width at least one coarse block.
+bool s9pair_ok(const OpView<float> &Df, const OpView<float> &Dc, int nu) {
+  if (nu != 2 || !ws9_ok<float>(Df, nu) || !ws9_ok<float>(Dc, nu)) return false;
+  if (Dc.nx * 2 != Df.nx || Dc.ny * 2 != Df.ny) return false;
+  return Df.nx % 4 == 0 && Df.ny % (2 * kD2TYC) == 0 && Dc.nx >= kD2TXC &&
+         Df.nx >= G9<2, kTY9, true>::TXO;
+}
+
+void s9down2(const OpView<float> &Df, const float *cls_f, const OpView<float> &Dc,
+             const float *cls_c, const float *b, float *xpre_f, float *b_c, float *xpre_c,
+             float *rcc, hipStream_t st) {
+  const S9Op<float> of = make_s9op(Df, cls_f), oc = make_s9op(Dc, cls_c);
+  const dim3 grid((Dc.nx + kD2TXC - 1) / kD2TXC, Dc.ny / kD2TYC);
+  k_s9down2<float><<<grid, 64 * kD2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, rcc);
+}
+
+void s9up2(const OpView<float> &Df, const float *cls_f, const OpView<float> &Dc,
+           const float *cls_c, const float *b, const float *xpre_f, const float *b_c,
+           const float *xpre_c, const float *ecc, float *x, hipStream_t st) {
+  using G = G9<2, kTY9, true>;
+  const S9Op<float> of = make_s9op(Df, cls_f), oc = make_s9op(Dc, cls_c);
+  const dim3 grid((Df.nx + G::TXO - 1) / G::TXO, Df.ny / (G::TY * kU2W));
+  k_s9up2<float><<<grid, 64 * kU2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, ecc, x);
+}
 template void s9up<double>(const OpView<double> &, const double *, int, const double *,
                            const double *, const double *, double *, hipStream_t);
 

@@ -45,7 +45,8 @@ class IRKSolver:
     def __init__(self, A, b, c, K, h_t, grid, precision="fp64", precond="LD", restart=40,
                  max_iter=200, nu_pre=2, nu_post=2, coarse_max=64, rtol=1e-8, true_resid=True,
                  reorth=0, side="right", M=None, interp="linear", graphs=None,
-                 coarse_ratio=None, smoother="rbgs", jacobi_omega=0.8, device=None):
+                 coarse_ratio=None, smoother="rbgs", jacobi_omega=0.8, fuse_levels=True,
+                 device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("IRKSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = B.lib()
@@ -76,6 +77,7 @@ class IRKSolver:
             opt.coarse_ratio = float(coarse_ratio)
         opt.smoother = B.SMOOTHER[smoother]
         opt.jacobi_omega = float(jacobi_omega)
+        opt.fuse_levels = 1 if fuse_levels else 0
         self.options = opt
         tab = B.Butcher(self.s, B.dptr(self.A), B.dptr(self._b), B.dptr(self._c))
         csr, keep = _csr_struct(*K)

@@ -48,6 +48,7 @@ def test_default_options():
     assert o.graphs == 0
     assert o.coarse_ratio == 2.0
     assert o.smoother == B.SMOOTHER["rbgs"] and o.jacobi_omega == 0.8
+    assert o.fuse_levels == 1
 
 
 def test_status_strings():
@@ -125,6 +126,10 @@ def test_setup_validation_before_any_device_work():
     opt.smoother, opt.jacobi_omega = B.SMOOTHER["jacobi"], 1.5
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
     assert st == B.IRK_E_INVALID and "jacobi_omega" in msg
+    opt = B.default_options()
+    opt.fuse_levels = 2
+    st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
+    assert st == B.IRK_E_INVALID and "fuse_levels" in msg
     opt = B.default_options()
     opt.side, opt.precision = B.IRK_LEFT, B.IRK_MIXED
     st, msg, _ = _setup_status(A, b, K, 0.01, (n, n), opt=opt)
