@@ -145,9 +145,11 @@ typedef struct {
                       D^-1 (b - D x), every node from the old values. */
   double jacobi_omega; /* Jacobi damping weight in (0, 1] (default 0.8) */
   int fuse_levels; /* 1: two adjacent intermediate nine-point levels share one
-                      launch per direction where the grid allows it (FP32
-                      V-cycles, nu = 2, red-black smoothing), the default.
-                      0: one launch per level.  The results are the same. */
+                      launch per direction where the grid allows it (nu = 2,
+                      red-black smoothing), the default.  0: one launch per
+                      level.  The operations per node are the same; FP32
+                      results may differ in the last bits where the compiler
+                      contracts a product and a sum differently. */
 } irk_options;
 
 typedef struct {

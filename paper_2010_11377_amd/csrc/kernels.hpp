@@ -168,18 +168,20 @@ template <typename T>
 void s9up(const OpView<T> &D, const T *classes, int nu, const T *b, const T *ec, const T *xpre,
           T *x, hipStream_t st);
 // Two adjacent nine-point levels F and C = F + 1 in one launch per direction
-// (FP32, nu = 2): s9down2 pre-smooths F from b, stores F's pre-smoothed x,
-// C's right-hand side b_c and pre-smoothed x, and C's restricted residual rcc
-// (the right-hand side of C + 1); s9up2 corrects C by ecc (the x of C + 1),
-// post-smooths it and then F, writing F's x.  Same results as s9down / s9up on
-// F then C (and C then F).  s9pair_ok tells whether the pair fits the tiling.
-bool s9pair_ok(const OpView<float> &Df, const OpView<float> &Dc, int nu);
-void s9down2(const OpView<float> &Df, const float *cls_f, const OpView<float> &Dc,
-             const float *cls_c, const float *b, float *xpre_f, float *b_c, float *xpre_c,
-             float *rcc, hipStream_t st);
-void s9up2(const OpView<float> &Df, const float *cls_f, const OpView<float> &Dc,
-           const float *cls_c, const float *b, const float *xpre_f, const float *b_c,
-           const float *xpre_c, const float *ecc, float *x, hipStream_t st);
+// (nu = 2, FP32 or FP64): s9down2 pre-smooths F from b, stores F's
+// pre-smoothed x, C's right-hand side b_c and pre-smoothed x, and C's
+// restricted residual rcc (the right-hand side of C + 1); s9up2 corrects C by
+// ecc (the x of C + 1), post-smooths it and then F, writing F's x.  The same
+// operations per node as s9down / s9up on F then C (and C then F).
+// s9pair_ok tells whether the pair fits the tiling.
+template <typename T>
+bool s9pair_ok(const OpView<T> &Df, const OpView<T> &Dc, int nu);
+template <typename T>
+void s9down2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cls_c,
+             const T *b, T *xpre_f, T *b_c, T *xpre_c, T *rcc, hipStream_t st);
+template <typename T>
+void s9up2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cls_c, const T *b,
+           const T *xpre_f, const T *b_c, const T *xpre_c, const T *ecc, T *x, hipStream_t st);
 // b = scale_j v_i - K (sum_k C[k] z_k) for a uniform five-point K on an
 // nx x ny grid with even nx (z and b float or double, FP64 arithmetic);
 // k_interior is a host copy of K's interior coefficients.

@@ -643,15 +643,11 @@ bool ws9_usable(const DevOp<T> &D, int nu) {
 // kernels of their own) run as one pair in each direction.
 template <typename T>
 bool pair_ok(const irk_solver *S, int i, int l) {
-  if constexpr (std::is_same_v<T, float>) {
-    if (!S->opt.fuse_levels || jacobi(S) || l < 1) return false;
-    const DevOp<float> &Df = Dops<float>(S)[i][l];
-    const DevOp<float> &Dc = Dops<float>(S)[i][l + 1];
-    return linear_p(Df) && linear_p(Dc) &&
-           irk::kern::s9pair_ok(Df.view(), Dc.view(), S->opt.nu_pre);
-  } else {
-    return false;
-  }
+  if (!S->opt.fuse_levels || jacobi(S) || l < 1) return false;
+  const DevOp<T> &Df = Dops<T>(S)[i][l];
+  const DevOp<T> &Dc = Dops<T>(S)[i][l + 1];
+  return linear_p(Df) && linear_p(Dc) &&
+         irk::kern::s9pair_ok<T>(Df.view(), Dc.view(), S->opt.nu_pre);
 }
 
 template <typename T>
@@ -708,9 +704,8 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
       const DevOp<T> &Dc = Dops<T>(S)[i][l + 1];
       const size_t nc = (size_t)Dc.nx * Dc.ny;
       ProfTok t = prof_begin(S, IRK_KC_VMID_DOWN, (double)(n + nc) * es * 1.25);
-      if constexpr (std::is_same_v<T, float>)
-        irk::kern::s9down2(D.view(), D.classes, Dc.view(), Dc.classes, bl(l), lev_p<T>(S, l),
-                           lev_b<T>(S, l + 1), lev_p<T>(S, l + 1), lev_b<T>(S, l + 2), st);
+      irk::kern::s9down2<T>(D.view(), D.classes, Dc.view(), Dc.classes, bl(l), lev_p<T>(S, l),
+                            lev_b<T>(S, l + 1), lev_p<T>(S, l + 1), lev_b<T>(S, l + 2), st);
       prof_end(S, t);
       ++l;
       continue;
@@ -773,9 +768,9 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
       const DevOp<T> &Df = Dops<T>(S)[i][l - 1];
       const size_t nf = (size_t)Df.nx * Df.ny;
       ProfTok t = prof_begin(S, IRK_KC_VMID_UP, (double)(n + nf) * es * 2.25);
-      if constexpr (std::is_same_v<T, float>)
-        irk::kern::s9up2(Df.view(), Df.classes, D.view(), D.classes, bl(l - 1), lev_p<T>(S, l - 1),
-                         bl(l), lev_p<T>(S, l), l == E ? zero : lev_x<T>(S, l + 1), xl(l - 1), st);
+      irk::kern::s9up2<T>(Df.view(), Df.classes, D.view(), D.classes, bl(l - 1),
+                          lev_p<T>(S, l - 1), bl(l), lev_p<T>(S, l),
+                          l == E ? zero : lev_x<T>(S, l + 1), xl(l - 1), st);
       prof_end(S, t);
       --l;
       continue;

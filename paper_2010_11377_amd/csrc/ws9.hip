@@ -26,6 +26,8 @@
 // zero.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace irk {
@@ -738,7 +740,9 @@ __global__ void __launch_bounds__(64 * kU2W)
   const int Jlo = ((OY - H) >> 1) - 1;  // first coarse row the fine tiles read
   const int wave = threadIdx.x >> 6, lane = l9();
 
-  // the fine tile's inputs first, so that their latency overlaps the coarse work
+  // in FP32 the fine tile's inputs are read first, so that their latency
+  // overlaps the coarse work; in FP64 they are read after it (register room)
+  constexpr bool kEarly = std::is_same_v<T, float>;
   Place p;
   p.OXn = OXn;
   p.OYn = OY + TY * wave;
@@ -751,8 +755,10 @@ __global__ void __launch_bounds__(64 * kU2W)
   p.fcol = OX == 0 && lane == G::HX / 2;
   p.lcol = OX == of.nx - G::TXO && lane == 63 - G::HX / 2;
   T9<T, R> t;
-  s9_load<T, R>(bf, t.ba, t.bb, p.X0, p.Y0, of.nx, of.ny);
-  s9_load<T, R>(xpre_f, t.xa, t.xb, p.X0, p.Y0, of.nx, of.ny);
+  if (kEarly) {
+    s9_load<T, R>(bf, t.ba, t.bb, p.X0, p.Y0, of.nx, of.ny);
+    s9_load<T, R>(xpre_f, t.xa, t.xb, p.X0, p.Y0, of.nx, of.ny);
+  }
 
   // ---- C: the rows read are Jlo .. Jlo + 14; wave 0 corrects and
   // post-smooths coarse rows Y0c .. Y0c + 15 (valid 4 .. 11), wave 1 rows
@@ -808,6 +814,10 @@ __global__ void __launch_bounds__(64 * kU2W)
   __syncthreads();
 
   // ---- F: the single-level up tile of wave w, C values from LDS
+  if (!kEarly) {
+    s9_load<T, R>(bf, t.ba, t.bb, p.X0, p.Y0, of.nx, of.ny);
+    s9_load<T, R>(xpre_f, t.xa, t.xb, p.X0, p.Y0, of.nx, of.ny);
+  }
   T cr[R / 2 + 3];
 #pragma unroll
   for (int q = 0; q < R / 2 + 3; ++q) cr[q] = xs[TY / 2 * wave + q][lane];
@@ -899,29 +909,45 @@ template void s9up<float>(const OpView<float> &, const float *, int, const float
 // Pairs: nu = 2, both levels on the register tiling, C = F / 2 exactly, F's
 // height a multiple of 16 (C's a multiple of the coarse block height) and
 // C's width at least one coarse block.
-bool s9pair_ok(const OpView<float> &Df, const OpView<float> &Dc, int nu) {
-  if (nu != 2 || !ws9_ok<float>(Df, nu) || !ws9_ok<float>(Dc, nu)) return false;
+template <typename T>
+bool s9pair_ok(const OpView<T> &Df, const OpView<T> &Dc, int nu) {
+  if (nu != 2 || !ws9_ok<T>(Df, nu) || !ws9_ok<T>(Dc, nu)) return false;
   if (Dc.nx * 2 != Df.nx || Dc.ny * 2 != Df.ny) return false;
   return Df.nx % 4 == 0 && Df.ny % (2 * kD2TYC) == 0 && Dc.nx >= kD2TXC &&
          Df.nx >= G9<2, kTY9, true>::TXO;
 }
 
-void s9down2(const OpView<float> &Df, const float *cls_f, const OpView<float> &Dc,
-             const float *cls_c, const float *b, float *xpre_f, float *b_c, float *xpre_c,
-             float *rcc, hipStream_t st) {
-  const S9Op<float> of = make_s9op(Df, cls_f), oc = make_s9op(Dc, cls_c);
+template <typename T>
+void s9down2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cls_c,
+             const T *b, T *xpre_f, T *b_c, T *xpre_c, T *rcc, hipStream_t st) {
+  const S9Op<T> of = make_s9op(Df, cls_f), oc = make_s9op(Dc, cls_c);
   const dim3 grid((Dc.nx + kD2TXC - 1) / kD2TXC, Dc.ny / kD2TYC);
-  k_s9down2<float><<<grid, 64 * kD2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, rcc);
+  k_s9down2<T><<<grid, 64 * kD2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, rcc);
 }
 
-void s9up2(const OpView<float> &Df, const float *cls_f, const OpView<float> &Dc,
-           const float *cls_c, const float *b, const float *xpre_f, const float *b_c,
-           const float *xpre_c, const float *ecc, float *x, hipStream_t st) {
+template <typename T>
+void s9up2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cls_c, const T *b,
+           const T *xpre_f, const T *b_c, const T *xpre_c, const T *ecc, T *x, hipStream_t st) {
   using G = G9<2, kTY9, true>;
-  const S9Op<float> of = make_s9op(Df, cls_f), oc = make_s9op(Dc, cls_c);
+  const S9Op<T> of = make_s9op(Df, cls_f), oc = make_s9op(Dc, cls_c);
   const dim3 grid((Df.nx + G::TXO - 1) / G::TXO, Df.ny / (G::TY * kU2W));
-  k_s9up2<float><<<grid, 64 * kU2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, ecc, x);
+  k_s9up2<T><<<grid, 64 * kU2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, ecc, x);
 }
+
+template bool s9pair_ok<float>(const OpView<float> &, const OpView<float> &, int);
+template bool s9pair_ok<double>(const OpView<double> &, const OpView<double> &, int);
+template void s9down2<float>(const OpView<float> &, const float *, const OpView<float> &,
+                             const float *, const float *, float *, float *, float *, float *,
+                             hipStream_t);
+template void s9down2<double>(const OpView<double> &, const double *, const OpView<double> &,
+                              const double *, const double *, double *, double *, double *,
+                              double *, hipStream_t);
+template void s9up2<float>(const OpView<float> &, const float *, const OpView<float> &,
+                           const float *, const float *, const float *, const float *,
+                           const float *, const float *, float *, hipStream_t);
+template void s9up2<double>(const OpView<double> &, const double *, const OpView<double> &,
+                            const double *, const double *, const double *, const double *,
+                            const double *, const double *, double *, hipStream_t);
 template void s9up<double>(const OpView<double> &, const double *, int, const double *,
                            const double *, const double *, double *, hipStream_t);
 

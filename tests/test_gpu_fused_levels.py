@@ -9,7 +9,7 @@ default) is compared with one without them (fuse_levels=False) on P_LD^-1 v
 for heat grids whose hierarchies pair every intermediate level (512^2 ..
 2048^2), ragged grids where only some levels pair (640 x 416, 512 x 256), a
 grid with no pair (256^2: the same bits), cycles that end inside a pair (small
-coarse ratios), and whole steps.  A wrong class, halo or hand-over would
+coarse ratios), and whole steps; in FP64 the two agree to 1e-13.  A wrong class, halo or hand-over would
 show as an O(1) error at the nodes it touches.  The oracle comparison of the
 V-cycle itself runs in test_gpu_parity.py on the default (paired) path.
 """
@@ -37,12 +37,12 @@ def dev():
     return torch.device("cuda", 0)
 
 
-def pair_of_solvers(nx, ny, dev, fam="gauss", s=7, h=1e-3, **kw):
+def pair_of_solvers(nx, ny, dev, fam="gauss", s=7, h=1e-3, precision="mixed", **kw):
     from paper_2010_11377_amd.solver import IRKSolver
     A, b, c = tableaux.tableau(fam, s)
     K = problems.heat(nx, ny=ny)
-    on = IRKSolver(A, b, c, K, h, (nx, ny), precision="mixed", device=dev, **kw)
-    off = IRKSolver(A, b, c, K, h, (nx, ny), precision="mixed", fuse_levels=False, device=dev,
+    on = IRKSolver(A, b, c, K, h, (nx, ny), precision=precision, device=dev, **kw)
+    off = IRKSolver(A, b, c, K, h, (nx, ny), precision=precision, fuse_levels=False, device=dev,
                     **kw)
     return on, off
 
@@ -55,18 +55,20 @@ def compare(z_on, z_off, nx, ny, tol=1e-5):
     return diff
 
 
-@pytest.mark.parametrize("nx,ny", [(256, 256), (512, 512), (1024, 1024), (2048, 2048),
-                                   (640, 416), (512, 256)])
-def test_paired_vcycle(dev, nx, ny):
-    say("case paired V-cycle", nx, ny)
-    on, off = pair_of_solvers(nx, ny, dev)
+@pytest.mark.parametrize("nx,ny,precision", [
+    (256, 256, "mixed"), (512, 512, "mixed"), (1024, 1024, "mixed"), (2048, 2048, "mixed"),
+    (640, 416, "mixed"), (512, 256, "mixed"), (512, 512, "fp64"), (1024, 1024, "fp64"),
+    (640, 416, "fp64")])
+def test_paired_vcycle(dev, nx, ny, precision):
+    say("case paired V-cycle", nx, ny, precision)
+    on, off = pair_of_solvers(nx, ny, dev, precision=precision)
     say("  hierarchy", on.info())
     v = torch.tensor(np.random.default_rng(12).standard_normal(7 * nx * ny), dtype=torch.float64,
                      device=dev)
     z_on = on.apply_preconditioner(v)
     z_off = off.apply_preconditioner(v)
     torch.cuda.synchronize()
-    diff = compare(z_on, z_off, nx, ny)
+    diff = compare(z_on, z_off, nx, ny, tol=1e-5 if precision == "mixed" else 1e-13)
     if nx == 256:  # levels 256, 128, then the tail: nothing pairs
         assert diff == 0
     on.close()
