@@ -224,12 +224,16 @@ irk_status irk_step_noalloc(irk_solver *S, const double *u_n_dev, double *u_np1_
 
 /* Discrete adjoint of irk_step (not in the paper): recomputes the forward
  * stages from the checkpoint u_n, solves the transposed stage system
- * (I + h A^T (x) K^T) psi = h (b (x) lam_np1) right-preconditioned by the
- * transposed preconditioner P^T (block back substitution for P_LD), and
- * writes lam_n = lam_np1 - K^T sum_i psi_i.  Optionally writes psi and the
- * stage values U_i = u_n + h sum_j a_ij k_j (device, s*N doubles each; NULL
- * skips).  Requires a symmetric K and M = I (IRK_E_INVALID otherwise).
- * lam_n_dev may alias lam_np1_dev. */
+ * (I (x) M^T + h A^T (x) K^T) psi = h (b (x) lam_np1) to the solver's
+ * tolerance, and writes lam_n = lam_np1 - K^T sum_i psi_i.  For a symmetric
+ * K and M = I the system is solved with this solver's operators,
+ * right-preconditioned by the transposed preconditioner P^T (block back
+ * substitution for P_LD); otherwise by a second solver of the same kind for
+ * the tableau A^T and the operators K^T, M^T (its preconditioner built from
+ * the LDU of A^T and the hierarchy of M^T + tau K^T), set up on the first
+ * such call (the library owns it; irk_update_operator and irk_destroy drop
+ * it).  Optionally writes psi and the stage values U_i = u_n + h sum_j a_ij k_j
+ * (device, s*N doubles each; NULL skips).  lam_n_dev may alias lam_np1_dev. */
 irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *lam_np1_dev,
                             double *lam_n_dev, double *psi_dev, double *U_dev, irk_stats *st);
 

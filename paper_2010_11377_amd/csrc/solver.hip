@@ -98,6 +98,11 @@ struct irk_solver {
   OpView<double> Mview{};
 
   // operators (rebuilt by irk_update_operator)
+  Stencil9 Kst;  // host copy of K, kept when the adjoint needs K^T (K not symmetric or M given)
+  // the transposed stage system (I (x) M^T + h A^T (x) K^T) psi = r as a stage
+  // system of its own (tableau A^T, operators K^T and M^T), set up on the first
+  // adjoint step that needs it and dropped when K changes
+  irk_solver *adj = nullptr;
   DevOp<double> K64;
   DevOp<float> K32;
   std::vector<std::vector<DevOp<double>>> D64;  // [stage][level]
@@ -359,6 +364,7 @@ irk_status build_operators(irk_solver *S, const irk_csr *K) {
   if (!irk::csr_to_stencil(K->n, K->rowptr, K->colind, K->val, S->nx, S->ny, K0, S->err))
     return IRK_E_INVALID;
   S->symmetric = irk::is_symmetric(K0, 1e-13);
+  S->Kst = (S->symmetric && !S->has_mass) ? Stencil9{} : K0;
   // hierarchy of S_l = R S_{l-1} P (S_0 = M) and K_l = R K_{l-1} P
   std::vector<Stencil9> Sl, Kl;
   Sl.push_back(S->has_mass ? S->Mst : irk::identity_stencil(S->nx, S->ny));
@@ -1578,6 +1584,8 @@ irk_status irk_update_operator(irk_solver *S, const irk_csr *K) {
       return IRK_E_INVALID;
     }
     const int old_levels = S->nlev;
+    irk_destroy(S->adj);  // its K^T is stale; set up again when needed
+    S->adj = nullptr;
     irk_status r = build_operators(S, K);
     if (r == IRK_OK && S->nlev != old_levels) {
       S->err = "hierarchy depth changed";
@@ -1665,18 +1673,79 @@ irk_status irk_step_noalloc(irk_solver *S, const double *u_n_dev, double *u_np1_
   return r;
 }
 
+// K^T (and M^T) as a stencil: the coefficient of node p towards neighbour
+// p + d is the coefficient of p + d towards p.
+static Stencil9 transposed(const Stencil9 &A) {
+  Stencil9 T;
+  T.resize(A.nx, A.ny);
+  for (int j = 0; j < A.ny; ++j)
+    for (int i = 0; i < A.nx; ++i)
+      for (int k = 0; k < 9; ++k) {
+        const int qi = i + irk::kdx(k), qj = j + irk::kdy(k);
+        double v = 0.0;
+        if (qi >= 0 && qi < A.nx && qj >= 0 && qj < A.ny)
+          v = A.c[8 - k][(size_t)qj * A.nx + qi];
+        T.c[k][(size_t)j * A.nx + i] = v;
+      }
+  return T;
+}
+
+struct HostCsr {
+  std::vector<int> rowptr, colind;
+  std::vector<double> val;
+  irk_csr view() const {
+    return irk_csr{(int)rowptr.size() - 1, (int)colind.size(), rowptr.data(), colind.data(),
+                   val.data()};
+  }
+};
+
+// Row-major CSR of a stencil (the diagonal always, other entries when nonzero).
+static HostCsr to_csr(const Stencil9 &A) {
+  HostCsr c;
+  c.rowptr.push_back(0);
+  for (int j = 0; j < A.ny; ++j)
+    for (int i = 0; i < A.nx; ++i) {
+      const size_t p = (size_t)j * A.nx + i;
+      for (int k = 0; k < 9; ++k) {
+        const int qi = i + irk::kdx(k), qj = j + irk::kdy(k);
+        if (qi < 0 || qi >= A.nx || qj < 0 || qj >= A.ny) continue;
+        const double v = A.c[k][p];
+        if (v == 0.0 && k != 4) continue;
+        c.colind.push_back(qj * A.nx + qi);
+        c.val.push_back(v);
+      }
+      c.rowptr.push_back((int)c.colind.size());
+    }
+  return c;
+}
+
+// The solver of the transposed stage system: tableau A^T, K^T, M^T, the
+// same grid, h_t, options and stream.
+static irk_status adjoint_solver(irk_solver *S) {
+  if (S->adj) return IRK_OK;
+  const int s = S->s;
+  double AT[64], c[8] = {};
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) AT[i * s + j] = S->A[j * s + i];
+  const irk_butcher tab{s, AT, S->b, c};
+  const HostCsr kt = to_csr(transposed(S->Kst));
+  HostCsr mt;
+  if (S->has_mass) mt = to_csr(transposed(S->Mst));
+  const irk_csr kv = kt.view(), mv = mt.view();
+  const irk_grid grid{S->nx, S->ny};
+  irk_status r = irk_setup(&S->adj, &tab, S->has_mass ? &mv : nullptr, &kv, S->h, &grid, &S->opt,
+                           S->stream);
+  if (r != IRK_OK) {
+    S->err = std::string("transposed stage system: ") + irk_last_error(nullptr);
+    S->adj = nullptr;
+  }
+  return r;
+}
+
 irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *lam_np1_dev,
                             double *lam_n_dev, double *psi_dev, double *U_dev, irk_stats *st) {
   if (!S || !u_n_dev || !lam_np1_dev || !lam_n_dev) return IRK_E_INVALID;
   return guarded(S, [&]() -> irk_status {
-    if (S->has_mass) {
-      S->err = "the adjoint step needs M = I";
-      return IRK_E_INVALID;
-    }
-    if (!S->symmetric) {
-      S->err = "the adjoint step needs a symmetric K";
-      return IRK_E_INVALID;
-    }
     const double t0 = now_s();
     irk_stats fst{}, ast{};
     // 1. forward stages from the checkpoint u_n
@@ -1685,15 +1754,28 @@ irk_status irk_adjoint_step(irk_solver *S, const double *u_n_dev, const double *
     if (r != IRK_OK) return r;
     if (!S->Ubuf) S->Ubuf = dalloc<double>(S->ws_allocs, S->sN);
     irk::kern::stage_values(u_n_dev, S->acc, S->hA, S->s, S->N, S->Ubuf, S->stream);
-    // 2. transposed stage system with rhs h (b (x) lam_{n+1})
-    irk::kern::scaled_broadcast(lam_np1_dev, S->hb, S->s, S->N, S->rhs, S->stream);
-    SystemDesc adj{S->hAT, S->Cadj, S->ord_adj, nullptr, false};
-    r = run_system(S, adj, &ast);
+    // 2. transposed stage system with rhs h (b (x) lam_{n+1}): for a
+    // symmetric K and M = I this solver's own operators with A^T and the
+    // transposed preconditioner; otherwise the solver of the transposed system
+    irk_solver *T = S;
+    if (S->symmetric && !S->has_mass) {
+      irk::kern::scaled_broadcast(lam_np1_dev, S->hb, S->s, S->N, S->rhs, S->stream);
+      SystemDesc adj{S->hAT, S->Cadj, S->ord_adj, nullptr, false};
+      r = run_system(S, adj, &ast);
+    } else {
+      r = adjoint_solver(S);
+      if (r != IRK_OK) return r;
+      T = S->adj;
+      irk::kern::scaled_broadcast(lam_np1_dev, S->hb, S->s, S->N, T->rhs, S->stream);
+      SystemDesc adj{T->hA, T->Cfwd, T->ord_fwd, nullptr, false};
+      r = run_system(T, adj, &ast);
+      if (r != IRK_OK && r != IRK_E_NOT_CONVERGED) S->err = "transposed stage system: " + T->err;
+    }
     if (r != IRK_OK && r != IRK_E_NOT_CONVERGED) return r;
-    // 3. lam_n = lam_{n+1} - K^T sum_i psi_i
-    irk::kern::adjoint_lambda(S->K64.view(), lam_np1_dev, S->acc, S->s, lam_n_dev, S->stream);
+    // 3. lam_n = lam_{n+1} - K^T sum_i psi_i (T's K is K^T, or K when symmetric)
+    irk::kern::adjoint_lambda(T->K64.view(), lam_np1_dev, T->acc, S->s, lam_n_dev, S->stream);
     if (psi_dev)
-      HIP_TRY(hipMemcpyAsync(psi_dev, S->acc, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
+      HIP_TRY(hipMemcpyAsync(psi_dev, T->acc, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
                              S->stream));
     if (U_dev)
       HIP_TRY(hipMemcpyAsync(U_dev, S->Ubuf, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1763,6 +1845,7 @@ irk_status irk_apply_preconditioner(irk_solver *S, const double *v_dev, double *
 void irk_destroy(irk_solver *S) {
   if (!S) return;
   (void)hipStreamSynchronize(S->stream);
+  irk_destroy(S->adj);
   for (const auto &t : S->prof_pending) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -10,7 +10,8 @@ five-point stiffness matrix).
 * one preconditioner application with V-cycle subsolves equals the oracle's
   V-cycle reading with the hierarchy started from M, and with a single level
   the exact ``P^-1 v``;
-* the adjoint (which assumes M = I) is refused;
+* the adjoint step (transposed stage system with M^T) matches the oracle's
+  transposed solve;
 * iteration counts stay flat in h_x at the paper's h_t rule (printed).
 """
 import sys
@@ -112,13 +113,32 @@ def test_mass_preconditioner_matches_oracle(dev, n, precision, coarse_max):
     assert err < (1e-11 if precision == "fp64" else 2e-5)
 
 
-def test_mass_adjoint_is_refused(dev):
-    from paper_2010_11377_amd.binding import IRKError
-    n = 16
-    S = solver(dev, "radau_iia", 2, n, 1e-2)
-    u = torch.zeros(n * n, dtype=torch.float64, device=dev)
-    with pytest.raises(IRKError):
-        S.adjoint_step(u, u.clone())
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mass_adjoint_matches_oracle(dev, precision):
+    """psi = (I (x) M + h A (x) K)^-T h (b (x) lam) and lam_n = lam - K^T sum psi
+    against the oracle's sparse LU of the transposed stage matrix."""
+    say("case mass adjoint", precision)
+    n, h = 48, 5e-3
+    S = solver(dev, "radau_iia", 3, n, h, precision=precision, rtol=1e-12)
+    rng = np.random.default_rng(31)
+    u = rng.standard_normal(n * n)
+    lam = rng.standard_normal(n * n)
+    ut = torch.tensor(u, dtype=torch.float64, device=dev)
+    lt = torch.tensor(lam, dtype=torch.float64, device=dev)
+    lam_n, psi, U = S.adjoint_step(ut, lt)
+    Ao, bo, _ = oracle_tableau("radau_iia", 3)
+    Mo, Ko = oracle_p1(n)
+    st = DirectStepper(Ao, bo, Ko, h, M=Mo)
+    psi_ref = st.adjoint_stages(h * np.outer(bo, lam))
+    lam_ref = lam - Ko.T @ psi_ref.sum(axis=0)
+    e_psi = np.linalg.norm(psi.cpu().numpy().ravel() - psi_ref.ravel()) / np.linalg.norm(psi_ref)
+    e_lam = np.linalg.norm(lam_n.cpu().numpy() - lam_ref) / np.linalg.norm(lam_ref)
+    say("  psi rel err %.2e  lam rel err %.2e" % (e_psi, e_lam))
+    assert e_psi <= 1e-9 and e_lam <= 1e-9
+    # the stage values come from the forward stages
+    k = st.stages(u)
+    Uref = u[None, :] + h * (Ao @ k)
+    assert np.linalg.norm(U.cpu().numpy() - Uref) <= 1e-9 * np.linalg.norm(Uref)
     S.close()
 
 
