@@ -647,11 +647,18 @@ bool ws9_usable(const DevOp<T> &D, int nu) {
 
 // Levels l and l + 1 (both intermediate: the finest level and the tail have
 // kernels of their own) run as one pair in each direction.
+// In FP64 a pair whose fine level is large runs slower than its two levels
+// apart (the pair kernels spill, and the fine tiles of a pair overlap more):
+// 1024^2 + 512^2 takes 23.0 + 21.1 us against about 16.5 + 18.5, while
+// 256^2 + 128^2 takes 8.9 + 15.1 against about 15.5 + 17.5.
+constexpr long long kPairMaxFine64 = 256 * 256;
+
 template <typename T>
 bool pair_ok(const irk_solver *S, int i, int l) {
   if (!S->opt.fuse_levels || jacobi(S) || l < 1) return false;
   const DevOp<T> &Df = Dops<T>(S)[i][l];
   const DevOp<T> &Dc = Dops<T>(S)[i][l + 1];
+  if (std::is_same_v<T, double> && (long long)Df.nx * Df.ny > kPairMaxFine64) return false;
   return linear_p(Df) && linear_p(Dc) &&
          irk::kern::s9pair_ok<T>(Df.view(), Dc.view(), S->opt.nu_pre);
 }
