@@ -85,9 +85,9 @@ def test_gradient_matches_oracle_adjoint(dev):
     J = 0.5 * torch.sum((uT - torch.tensor(u_tgt, device=dev)) ** 2)
     J.backward()
     g = kt.grad.cpu().numpy()
-    say("  J %.6e (oracle %.6e), grad rel err %.2e" % (float(J), J_ref,
+    say("  J %.6e (oracle %.6e), grad rel err %.2e" % (float(J.detach()), J_ref,
         np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)))
-    assert abs(float(J) - J_ref) <= 1e-9 * J_ref
+    assert abs(float(J.detach()) - J_ref) <= 1e-9 * J_ref
     assert np.linalg.norm(g - g_ref) <= 1e-7 * np.linalg.norm(g_ref)
     S.close()
 
