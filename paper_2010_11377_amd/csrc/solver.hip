@@ -1446,7 +1446,7 @@ void irk_default_options(irk_options *o) {
   o->side = IRK_RIGHT;
   o->interp = IRK_INTERP_LINEAR;
   o->graphs = 0;
-  o->coarse_ratio = 2.0;
+  o->coarse_ratio = 8.0;
   o->smoother = IRK_SMOOTH_RBGS;
   o->jacobi_omega = 0.8;
   o->fuse_levels = 1;

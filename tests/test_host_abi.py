@@ -46,7 +46,7 @@ def test_default_options():
     assert o.side == B.IRK_RIGHT
     assert o.interp == B.IRK_INTERP_LINEAR
     assert o.graphs == 0
-    assert o.coarse_ratio == 2.0
+    assert o.coarse_ratio == 8.0
     assert o.smoother == B.SMOOTHER["rbgs"] and o.jacobi_omega == 0.8
     assert o.fuse_levels == 1
 
