@@ -176,6 +176,13 @@ void s9up(const OpView<T> &D, const T *classes, int nu, const T *b, const T *ec,
 // s9pair_ok tells whether the pair fits the tiling.
 template <typename T>
 bool s9pair_ok(const OpView<T> &Df, const OpView<T> &Dc, int nu);
+// The last level of a cycle that ends above the coarsest level (nine-point
+// classes, nu = 2): x = post-smoothing of the pre-smoothing from zero of b,
+// the level's V-cycle with a zero coarse correction, in one pass.
+template <typename T>
+bool s9smooth_ok(const OpView<T> &D, int nu);
+template <typename T>
+void s9smooth(const OpView<T> &D, const T *classes, const T *b, T *x, hipStream_t st);
 template <typename T>
 void s9down2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cls_c,
              const T *b, T *xpre_f, T *b_c, T *xpre_c, T *rcc, hipStream_t st);

@@ -663,6 +663,15 @@ bool pair_ok(const irk_solver *S, int i, int l) {
          irk::kern::s9pair_ok<T>(Df.view(), Dc.view(), S->opt.nu_pre);
 }
 
+// The one-pass smoothing of a cycle's last level (red-black, linear
+// interpolation, nine-point classes).
+template <typename T>
+bool smooth_ok(const irk_solver *S, int i, int l) {
+  if (!S->opt.fuse_levels || jacobi(S) || l < 1) return false;
+  const DevOp<T> &D = Dops<T>(S)[i][l];
+  return linear_p(D) && irk::kern::s9smooth_ok<T>(D.view(), S->opt.nu_pre);
+}
+
 template <typename T>
 void down_pass(const DevOp<T> &D, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
   if (D.jw > T(0)) return irk::kern::vdown<T>(D.view(), nu, b, rc, st);  // damped Jacobi
@@ -736,7 +745,15 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
     down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
     prof_end(S, t);
   }
-  if (tail) {
+  if (tail && ends && E == S->lt && smooth_ok<T>(S, i, E)) {
+    // the cycle ends on the tail's first level: its smoothing alone, on many
+    // workgroups instead of the one-workgroup tail
+    const DevOp<T> &D = Dops<T>(S)[i][E];
+    const size_t n = (size_t)D.nx * D.ny;
+    ProfTok t = prof_begin(S, IRK_KC_VTAIL, (double)n * es * 2.0);
+    irk::kern::s9smooth<T>(D.view(), D.classes, bl(E), xl(E), st);
+    prof_end(S, t);
+  } else if (tail) {
     irk::TailDesc<T> td{};
     td.nlev = Lt - lt;
     size_t off = 0, words = 0;

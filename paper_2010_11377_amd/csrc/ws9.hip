@@ -513,6 +513,77 @@ dim3 grid9(int nx, int ny) {
 }
 
 // ===========================================================================
+// The last level of a cycle that ends above the coarsest level: its V(nu, nu)
+// with a zero coarse correction is the pre-smoothing from x = 0 followed by
+// the post-smoothing, 4 nu - 1 half sweeps after the first, in one pass with
+// a halo of that depth.  Tiles of 8 rows with a halo of 8: a boundary row can
+// sit in another tile only on its never-relaxed edge row, whose wrong class
+// reaches 7 rows in.  Column classes per lane from the global column, so any
+// width works (a single tile column when the grid is narrower than one).
+template <int NU_>
+struct G9S {
+  static constexpr int NU = NU_, TY = 8, H = ev9(4 * NU_ - 1), HX = H;
+  static constexpr int R = TY + 2 * H;
+  static constexpr int TXO = 128 - 2 * HX;
+};
+
+template <typename T, bool BOUND, int R, int H, int TY, int YB, int NU>
+__device__ __forceinline__ void s9_smooth_tile(const S9Op<T> &o, const Place &p,
+                                               const MidCo<T> &m, T9<T, R> &t) {
+  const Ctx<T, BOUND, R, H, TY, YB> cx{o, p, m};
+  s9_pre<T, BOUND, R, H, TY, YB, NU>(cx, t);
+  s9_post<T, BOUND, R, H, TY, YB, NU>(cx, t);
+}
+
+template <typename T, int NU>
+__global__ void __launch_bounds__(64 * kW9)
+    k_s9smooth(S9Op<T> o, const T *__restrict__ bin, T *__restrict__ xout) {
+  using G = G9S<NU>;
+  using V = typename P9<T>::V;
+  constexpr int H = G::H, R = G::R, TY = G::TY;
+  const int wave = threadIdx.x >> 6, lane = l9();
+  const Tile2 tile = xcd_tile();
+  Place p;
+  p.OXn = tile.x * G::TXO;
+  p.OYn = (tile.y * kW9 + wave) * TY;
+  if (p.OYn >= o.ny) return;
+  const int OX = max(0, min(p.OXn, o.nx - G::TXO));
+  p.X0 = OX - G::HX;
+  p.Y0 = p.OYn - H;
+  p.lo = G::HX / 2;
+  p.hi = 64 - G::HX / 2;
+  p.top = p.OYn == 0;
+  p.bot = p.OYn == o.ny - TY;
+  p.fcol = p.X0 + 2 * lane == 0;
+  p.lcol = p.X0 + 2 * lane + 1 == o.nx - 1;
+  T9<T, R> t;
+  s9_load<T, R>(bin, t.ba, t.bb, p.X0, p.Y0, o.nx, o.ny);
+  if (!boundary_tile(p, R, o.nx, o.ny)) {
+    s9_smooth_tile<T, false, R, H, TY, 0, NU>(o, p, MidCo<T>{}, t);
+  } else {
+    const MidCo<T> m = mid_coefs(o, p);
+    if (p.top && p.bot)
+      s9_smooth_tile<T, true, R, H, TY, 3, NU>(o, p, m, t);
+    else if (p.top)
+      s9_smooth_tile<T, true, R, H, TY, 1, NU>(o, p, m, t);
+    else if (p.bot)
+      s9_smooth_tile<T, true, R, H, TY, 2, NU>(o, p, m, t);
+    else
+      s9_smooth_tile<T, true, R, H, TY, 0, NU>(o, p, m, t);
+  }
+  const int gxa = p.X0 + 2 * lane;
+  if (lane >= p.lo && lane < p.hi && gxa >= p.OXn && gxa < o.nx) {
+#pragma unroll
+    for (int r = H; r < H + TY; ++r) {
+      V v;
+      v.x = t.xa[r];
+      v.y = t.xb[r];
+      *reinterpret_cast<V *>(xout + (size_t)(p.Y0 + r) * o.nx + gxa) = v;
+    }
+  }
+}
+
+// ===========================================================================
 // Two adjacent levels in one launch (nu = 2), the fine level F and its coarse
 // level C = F + 1, both nine-point with constant coefficients per class.
 //
@@ -933,6 +1004,29 @@ void s9up2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cl
   const dim3 grid((Df.nx + G::TXO - 1) / G::TXO, Df.ny / (G::TY * kU2W));
   k_s9up2<T><<<grid, 64 * kU2W, 0, st>>>(of, oc, b, xpre_f, b_c, xpre_c, ecc, x);
 }
+
+// The end-level pass: nine-point classes, linear interpolation, nu = 2, even
+// width, height a multiple of the tile height.
+template <typename T>
+bool s9smooth_ok(const OpView<T> &D, int nu) {
+  return nu == 2 && D.npt == 9 && D.cls && !D.arr && D.nx % 2 == 0 && D.nx >= 2 &&
+         D.ny % G9S<2>::TY == 0;
+}
+
+template <typename T>
+void s9smooth(const OpView<T> &D, const T *classes, const T *b, T *x, hipStream_t st) {
+  using G = G9S<2>;
+  const S9Op<T> o = make_s9op(D, classes);
+  const dim3 grid((D.nx + G::TXO - 1) / G::TXO, (D.ny + G::TY * kW9 - 1) / (G::TY * kW9));
+  k_s9smooth<T, 2><<<grid, 64 * kW9, 0, st>>>(o, b, x);
+}
+
+template bool s9smooth_ok<float>(const OpView<float> &, int);
+template bool s9smooth_ok<double>(const OpView<double> &, int);
+template void s9smooth<float>(const OpView<float> &, const float *, const float *, float *,
+                              hipStream_t);
+template void s9smooth<double>(const OpView<double> &, const double *, const double *, double *,
+                               hipStream_t);
 
 template bool s9pair_ok<float>(const OpView<float> &, const OpView<float> &, int);
 template bool s9pair_ok<double>(const OpView<double> &, const OpView<double> &, int);
