@@ -49,9 +49,9 @@ SPMM_UPDATE_TRAFFIC = {
     "source": os.path.join("paper_2010_11377_amd", "csrc", "kernels.hip"),
     "begin": "// Kronecker SpMM with fused Gram-Schmidt",
     "end": "// Second Gram-Schmidt pass on the new column",
-    "sha256": "d07ff6a517456b16fa30672d8d486aed43968849dc4d57892e7233420dad51a1",
-    "fetch_kib": (1.9999 * 58533.7, 1.9999 * 121253.6),  # a + b (j + 1), scaled
-    "write_kib": 229950.8,
+    "sha256": "dcf5117c4461b805b33fbb3ba955e3c0ad138ac7529f0c938daf91db6945a23d",
+    "fetch_kib": (1.9999 * 69957.3, 1.9999 * 114688.3),  # a + b (j + 1), scaled
+    "write_kib": 229904.1,
 }
 
 

@@ -245,12 +245,45 @@ __device__ __forceinline__ void kron_apply(const OpView<double> &K, const OpView
   }
 }
 
+// Block sums of NV values at once (one pair of barriers); each value is
+// summed in the order block_sum uses.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV]) {
+  __shared__ double red[NV][kBlock / 64];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < kBlock / 64; ++q) r += red[k][q];
+    }
+    v[k] = r;
+  }
+}
+
+// The basis columns are read once per pass and the new column is not read
+// again before the next pass: non-temporal loads and stores keep them from
+// displacing the stencil's z rows in the caches (measured at 2048^2, seven
+// stages: update 341 -> 299 us, dots 274 -> 239 us with four columns per
+// block reduction).
 template <typename TZ, int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
     k_spmm_dots(OpView<double> K, OpView<double> M, const TZ *__restrict__ z, Mat8 hA,
                 const double *__restrict__ V,
                 const double *__restrict__ scale, const KrylovState *__restrict__ ks,
                 double *__restrict__ partial) {
+  constexpr int NV = 4;  // columns per block reduction
   const size_t N = (size_t)K.nx * K.ny;
   const size_t sN = (size_t)S * N;
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -259,16 +292,25 @@ __global__ void __launch_bounds__(kBlock)
   double w[S];
   const bool live = p < N;
   if (live) kron_apply<TZ, S, MASS>(K, M, z + (size_t)jj * sN, hA, p, N, w);
-  for (int m = 0; m <= jj; ++m) {
-    double acc = 0.0;
-    if (live) {
-      const double *Vm = V + (size_t)m * sN;
+  for (int m0 = 0; m0 <= jj; m0 += NV) {
+    double acc[NV];
 #pragma unroll
-      for (int r = 0; r < S; ++r) acc += Vm[(size_t)r * N + p] * w[r];
-      acc *= scale[m];
+    for (int u = 0; u < NV; ++u) {
+      const int m = m0 + u;
+      acc[u] = 0.0;
+      if (live && m <= jj) {
+        const double *Vm = V + (size_t)m * sN;
+#pragma unroll
+        for (int r = 0; r < S; ++r) acc[u] += __builtin_nontemporal_load(Vm + (size_t)r * N + p) * w[r];
+        acc[u] *= scale[m];
+      }
     }
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) partial[(size_t)m * nblk + blockIdx.x] = t;
+    block_sums<NV>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int u = 0; u < NV; ++u)
+        if (m0 + u <= jj) partial[(size_t)(m0 + u) * nblk + blockIdx.x] = acc[u];
+    }
   }
   // ||w||^2 as column j+1: lets the device decide on a second Gram-Schmidt pass
   double ww = 0.0;
@@ -298,12 +340,12 @@ __global__ void __launch_bounds__(kBlock)
       const double c = hcol[m] * scale[m];
       const double *Vm = V + (size_t)m * sN;
 #pragma unroll
-      for (int r = 0; r < S; ++r) w[r] -= c * Vm[(size_t)r * N + p];
+      for (int r = 0; r < S; ++r) w[r] -= c * __builtin_nontemporal_load(Vm + (size_t)r * N + p);
     }
     double *vout = Vall + (size_t)(jj + 1) * sN;
 #pragma unroll
     for (int r = 0; r < S; ++r) {
-      vout[(size_t)r * N + p] = w[r];
+      __builtin_nontemporal_store(w[r], vout + (size_t)r * N + p);
       val += w[r] * w[r];
     }
   }
