@@ -154,6 +154,12 @@ void sdown(const OpView<float> &D, const float *interior, int nu, const float *b
            hipStream_t st);
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st);
+// The same passes for a block without coupling terms: the right-hand side is
+// float(*vscale * v) formed on load from the FP64 vector v.
+void sdown_v(const OpView<float> &D, const float *interior, int nu, const double *v,
+             const double *vscale, float *rc, hipStream_t st);
+void sup_v(const OpView<float> &D, const float *interior, int nu, const double *v,
+           const double *vscale, const float *ec, float *x, hipStream_t st);
 // Nine-point constant-coefficient levels, two columns per lane, FP32 or
 // FP64 (ws9.hip); `classes` is a host copy of the 81 class coefficients.
 // The down pass stores its pre-smoothed x in xpre (a level-sized buffer),
@@ -203,11 +209,13 @@ void scouple_var(int nx, int ny, const double *karr, const double *v, const doub
 // Finest-level down pass of stage block `stage`: pre-smoothing from x = 0,
 // rc = R (b - D x), and the pre-smoothed x of every node into xpre.  nx, ny
 // even.  Up pass: x = xpre + P ec, then the post-smoothing (wfine.hip).
+// bscale (device, may be null): the right-hand side is *bscale times b.
 template <typename T>
-void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st);
+void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st,
+           const double *bscale = nullptr);
 template <typename T>
 void fup(const FineOp<T> &F, int stage, int nu, const T *b, const T *xpre, const T *ec, T *x,
-         hipStream_t st);
+         hipStream_t st, const double *bscale = nullptr);
 // y[j] *= scale[j], j < k (left.hip).
 void scale_by(double *y, const double *scale, int k, hipStream_t st);
 // The FP32 tail with rows in registers (tail2.hip): levels of at most 64 x 64

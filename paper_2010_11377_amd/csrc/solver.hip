@@ -705,8 +705,12 @@ void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, 
 // workgroup, fused up passes back.  The cycle ends at level E = cycle_end[i]:
 // E takes its smoothing with a zero coarse correction (an up pass from the
 // zero vector, or a tail whose coarsest level returns zero).
+// v0 (a block without coupling terms, finest level on the FP32 split passes
+// or the FP64 passes that keep the pre-smoothed x): the finest level's
+// right-hand side is *v0scale * v0 rounded to T, formed by its passes on load.
 template <typename T>
-void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
+void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done,
+            const double *v0 = nullptr, const double *v0scale = nullptr) {
   hipStream_t st = S->stream;
   const int nu = S->opt.nu_pre, L = S->nlev;
   const int E = S->cycle_end[i];
@@ -736,13 +740,29 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
       // b and K per node (read) in, the coarse residual and the pre-smoothed x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
       ProfTok t = prof_begin(S, IRK_KC_VDOWN_L0, (double)n * es * 2.25 + kb);
+      if constexpr (std::is_same_v<T, double>) {
+        if (v0) {
+          irk::kern::fdown<T>(fine_op<T>(S), i, nu, v0, lev_b<T>(S, 1), lev_p<T>(S, 0), st,
+                              v0scale);
+          prof_end(S, t);
+          continue;
+        }
+      }
       irk::kern::fdown<T>(fine_op<T>(S), i, nu, b, lev_b<T>(S, 1), lev_p<T>(S, 0), st);
       prof_end(S, t);
       continue;
     }
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VDOWN_L0 : IRK_KC_VMID_DOWN,
-                           (double)n * es * 1.25 + op_bytes(S, n, D.npt, es));
-    down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
+                           (double)n * (l == 0 && v0 ? 8.0 + es * 0.25 : es * 1.25) +
+                               op_bytes(S, n, D.npt, es));
+    if constexpr (std::is_same_v<T, float>) {
+      if (l == 0 && v0)
+        irk::kern::sdown_v(D.view(), D.interior, nu, v0, v0scale, lev_b<T>(S, 1), st);
+      else
+        down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
+    } else {
+      down_pass<T>(D, nu, bl(l), lev_b<T>(S, l + 1), lev_p<T>(S, l), st);
+    }
     prof_end(S, t);
   }
   if (tail && ends && E == S->lt && smooth_ok<T>(S, i, E)) {
@@ -809,14 +829,30 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done) {
       // b, the pre-smoothed x, K per node and the coarse correction in, x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
       ProfTok t = prof_begin(S, IRK_KC_VUP_L0, (double)n * es * 3.25 + kb);
-      irk::kern::fup<T>(fine_op<T>(S), i, nu, b, lev_p<T>(S, 0),
-                        l == E ? zero : lev_x<T>(S, 1), x, st);
+      const T *ec0 = l == E ? zero : lev_x<T>(S, 1);
+      if constexpr (std::is_same_v<T, double>) {
+        if (v0) {
+          irk::kern::fup<T>(fine_op<T>(S), i, nu, v0, lev_p<T>(S, 0), ec0, x, st, v0scale);
+          prof_end(S, t);
+          continue;
+        }
+      }
+      irk::kern::fup<T>(fine_op<T>(S), i, nu, b, lev_p<T>(S, 0), ec0, x, st);
       prof_end(S, t);
       continue;
     }
     ProfTok t = prof_begin(S, l == 0 ? IRK_KC_VUP_L0 : IRK_KC_VMID_UP,
-                           (double)n * es * 2.25 + op_bytes(S, n, D.npt, es));
-    up_pass<T>(D, nu, bl(l), l == E ? zero : lev_x<T>(S, l + 1), lev_p<T>(S, l), xl(l), st);
+                           (double)n * (l == 0 && v0 ? 8.0 + es * 1.25 : es * 2.25) +
+                               op_bytes(S, n, D.npt, es));
+    const T *ec = l == E ? zero : lev_x<T>(S, l + 1);
+    if constexpr (std::is_same_v<T, float>) {
+      if (l == 0 && v0)
+        irk::kern::sup_v(D.view(), D.interior, nu, v0, v0scale, ec, xl(l), st);
+      else
+        up_pass<T>(D, nu, bl(l), ec, lev_p<T>(S, l), xl(l), st);
+    } else {
+      up_pass<T>(D, nu, bl(l), ec, lev_p<T>(S, l), xl(l), st);
+    }
     prof_end(S, t);
   }
 }
@@ -863,6 +899,12 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
                                 S->s, i, b0, S->stream);
       prof_end(S, tk);
       vcycle<T>(S, i, b0, z + (size_t)i * N, false);
+    } else if (ncoup == 0 && D0 && !jacobi(S) &&
+               ((std::is_same_v<T, float> && split_ok<T>(*D0) && !S->fine_mode) ||
+                (std::is_same_v<T, double> && S->fine_mode == 1))) {
+      // no coupling terms: the finest passes form scale_j v_i (rounded to the
+      // V-cycle's precision) on load
+      vcycle<T>(S, i, nullptr, z + (size_t)i * N, false, v + (size_t)i * N, scale_j);
     } else if ((S->fine_mode == 1 && kcouple_ok(S)) ||
                (D0 && split_ok<T>(*D0) && split_ok<T>(Kdev<T>(S))) || split64) {
       // streaming coupling pass, then the plain V-cycle (FP32: two columns per

@@ -268,9 +268,24 @@ __device__ __forceinline__ void f_down_tile(const FOp<T> &o, FTile<T, FGeomD<T, 
   }
 }
 
+// bscale (may be null): b is *bscale times the vector bin, scaled on load
+// (the right-hand side of a block without coupling terms in FP64, the same
+// bits the coupling pass would write).
+template <typename T, int R>
+__device__ __forceinline__ void f_scale_b(const double *bscale, FTile<T, R> &t) {
+  if (!bscale) return;
+  const T sc = (T)*bscale;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    t.ba[r] = sc * t.ba[r];
+    t.bb[r] = sc * t.bb[r];
+  }
+}
+
 template <typename T, bool VAR, int NU>
 __global__ void __launch_bounds__(64 * kFW)
-    k_fdown(FOp<T> o, const T *__restrict__ bin, T *__restrict__ rc, T *__restrict__ xpre) {
+    k_fdown(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ bscale,
+            T *__restrict__ rc, T *__restrict__ xpre) {
   using G = FGeomD<T, NU, VAR>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Tile2 tile = xcd_tile();
@@ -279,6 +294,7 @@ __global__ void __launch_bounds__(64 * kFW)
   const int X0 = OX - G::H, Y0 = OY - G::H;
   FTile<T, G::R> t;
   f_load<T, G::R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  f_scale_b<T, G::R>(bscale, t);
   if (X0 >= 0 && Y0 >= 0 && X0 + 128 <= o.nx && Y0 + G::R <= o.ny)
     f_down_tile<T, VAR, false, NU>(o, t, X0, Y0, rc, xpre);
   else
@@ -334,8 +350,8 @@ __device__ __forceinline__ void f_up_tile(const FOp<T> &o, FTile<T, FGeomU<T, NU
 
 template <typename T, bool VAR, int NU>
 __global__ void __launch_bounds__(64 * kFW)
-    k_fup(FOp<T> o, const T *__restrict__ bin, const T *__restrict__ xpre,
-          const T *__restrict__ ec, T *__restrict__ xout) {
+    k_fup(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ bscale,
+          const T *__restrict__ xpre, const T *__restrict__ ec, T *__restrict__ xout) {
   using G = FGeomU<T, NU, VAR>;
   constexpr int R = G::R;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -347,6 +363,7 @@ __global__ void __launch_bounds__(64 * kFW)
   const int ncx = o.nx / 2, ncy = o.ny / 2;
   FTile<T, R> t;
   f_load<T, R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  f_scale_b<T, R>(bscale, t);
   f_load<T, R>(xpre, t.xa, t.xb, X0, Y0, o.nx, o.ny);
   T cr[R / 2 + 3];
   {
@@ -390,12 +407,15 @@ FOp<T> make_fop(const FineOp<T> &F, int stage) {
 }
 
 template <typename T, bool VAR, int NU>
-void fdown_launch(const FOp<T> &o, const T *b, T *rc, T *xpre, hipStream_t st) {
-  k_fdown<T, VAR, NU><<<f_grid<FGeomD<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, rc, xpre);
+void fdown_launch(const FOp<T> &o, const T *b, const double *bs, T *rc, T *xpre, hipStream_t st) {
+  k_fdown<T, VAR, NU><<<f_grid<FGeomD<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, bs, rc,
+                                                                                  xpre);
 }
 template <typename T, bool VAR, int NU>
-void fup_launch(const FOp<T> &o, const T *b, const T *xpre, const T *ec, T *x, hipStream_t st) {
-  k_fup<T, VAR, NU><<<f_grid<FGeomU<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, xpre, ec, x);
+void fup_launch(const FOp<T> &o, const T *b, const double *bs, const T *xpre, const T *ec, T *x,
+                hipStream_t st) {
+  k_fup<T, VAR, NU><<<f_grid<FGeomU<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, bs, xpre,
+                                                                                ec, x);
 }
 
 }  // namespace
@@ -403,42 +423,43 @@ void fup_launch(const FOp<T> &o, const T *b, const T *xpre, const T *ec, T *x, h
 namespace kern {
 
 template <typename T>
-void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st) {
+void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st,
+           const double *bscale) {
   const FOp<T> o = make_fop(F, stage);
   if (F.kq) {
-    if (nu == 1) fdown_launch<T, true, 1>(o, b, rc, xpre, st);
-    else if (nu == 2) fdown_launch<T, true, 2>(o, b, rc, xpre, st);
-    else fdown_launch<T, true, 3>(o, b, rc, xpre, st);
+    if (nu == 1) fdown_launch<T, true, 1>(o, b, bscale, rc, xpre, st);
+    else if (nu == 2) fdown_launch<T, true, 2>(o, b, bscale, rc, xpre, st);
+    else fdown_launch<T, true, 3>(o, b, bscale, rc, xpre, st);
   } else {
-    if (nu == 1) fdown_launch<T, false, 1>(o, b, rc, xpre, st);
-    else if (nu == 2) fdown_launch<T, false, 2>(o, b, rc, xpre, st);
-    else fdown_launch<T, false, 3>(o, b, rc, xpre, st);
+    if (nu == 1) fdown_launch<T, false, 1>(o, b, bscale, rc, xpre, st);
+    else if (nu == 2) fdown_launch<T, false, 2>(o, b, bscale, rc, xpre, st);
+    else fdown_launch<T, false, 3>(o, b, bscale, rc, xpre, st);
   }
 }
 
 template <typename T>
 void fup(const FineOp<T> &F, int stage, int nu, const T *b, const T *xpre, const T *ec, T *x,
-         hipStream_t st) {
+         hipStream_t st, const double *bscale) {
   const FOp<T> o = make_fop(F, stage);
   if (F.kq) {
-    if (nu == 1) fup_launch<T, true, 1>(o, b, xpre, ec, x, st);
-    else if (nu == 2) fup_launch<T, true, 2>(o, b, xpre, ec, x, st);
-    else fup_launch<T, true, 3>(o, b, xpre, ec, x, st);
+    if (nu == 1) fup_launch<T, true, 1>(o, b, bscale, xpre, ec, x, st);
+    else if (nu == 2) fup_launch<T, true, 2>(o, b, bscale, xpre, ec, x, st);
+    else fup_launch<T, true, 3>(o, b, bscale, xpre, ec, x, st);
   } else {
-    if (nu == 1) fup_launch<T, false, 1>(o, b, xpre, ec, x, st);
-    else if (nu == 2) fup_launch<T, false, 2>(o, b, xpre, ec, x, st);
-    else fup_launch<T, false, 3>(o, b, xpre, ec, x, st);
+    if (nu == 1) fup_launch<T, false, 1>(o, b, bscale, xpre, ec, x, st);
+    else if (nu == 2) fup_launch<T, false, 2>(o, b, bscale, xpre, ec, x, st);
+    else fup_launch<T, false, 3>(o, b, bscale, xpre, ec, x, st);
   }
 }
 
 template void fdown<float>(const FineOp<float> &, int, int, const float *, float *, float *,
-                           hipStream_t);
+                           hipStream_t, const double *);
 template void fup<float>(const FineOp<float> &, int, int, const float *, const float *,
-                         const float *, float *, hipStream_t);
+                         const float *, float *, hipStream_t, const double *);
 template void fdown<double>(const FineOp<double> &, int, int, const double *, double *, double *,
-                            hipStream_t);
+                            hipStream_t, const double *);
 template void fup<double>(const FineOp<double> &, int, int, const double *, const double *,
-                          const double *, double *, hipStream_t);
+                          const double *, double *, hipStream_t, const double *);
 
 }  // namespace kern
 }  // namespace irk

@@ -133,6 +133,42 @@ __device__ __forceinline__ void s_load(const float *__restrict__ g, float (&a)[R
   }
 }
 
+// The right-hand side of a block without coupling terms is scale_j v_i
+// rounded to FP32, formed here on load from the FP64 Krylov vector (the same
+// bits the coupling pass would write), so that block needs no pass of its own.
+template <int R>
+__device__ __forceinline__ void s_load_scaled(const double *__restrict__ g, double sc,
+                                              float (&a)[R], float (&b)[R], int X0, int Y0,
+                                              int nx, int ny) {
+  const int gx = X0 + 2 * s_lane();
+  const bool inx = gx >= 0 && gx < nx;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = Y0 + r;
+    double2 v = make_double2(0.0, 0.0);
+    if (inx && gy >= 0 && gy < ny) v = *reinterpret_cast<const double2 *>(g + (size_t)gy * nx + gx);
+    a[r] = (float)(sc * v.x);
+    b[r] = (float)(sc * v.y);
+  }
+}
+
+// Right-hand side source of the finest-level passes: FP32 b, or (VIN) FP64 v
+// scaled by *vscale.
+struct BIn {
+  const float *b;
+  const double *v;
+  const double *vscale;
+};
+
+template <bool VIN, int R>
+__device__ __forceinline__ void s_load_b(const BIn &in, float (&a)[R], float (&b)[R], int X0,
+                                         int Y0, int nx, int ny) {
+  if (VIN)
+    s_load_scaled<R>(in.v, *in.vscale, a, b, X0, Y0, nx, ny);
+  else
+    s_load<R>(in.b, a, b, X0, Y0, nx, ny);
+}
+
 __device__ __forceinline__ bool s_interior(int X0, int Y0, int R, int nx, int ny) {
   return X0 >= 0 && Y0 >= 0 && X0 + 128 <= nx && Y0 + R <= ny;
 }
@@ -209,9 +245,9 @@ __device__ __forceinline__ void s_down_rows(const SOp &o, STile<R> &t, int X0, i
   }
 }
 
-template <int NU>
+template <int NU, bool VIN>
 __global__ void __launch_bounds__(64 * kSW)
-    k_sdown(SOp o, const float *__restrict__ bin, float *__restrict__ rc) {
+    k_sdown(SOp o, BIn bin, float *__restrict__ rc) {
   using G = SGeomD<NU>;
   constexpr int H = G::H, TY = G::TY, R = G::R;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // Y0 uniform
@@ -220,7 +256,7 @@ __global__ void __launch_bounds__(64 * kSW)
   if (OY >= o.ny) return;
   const int X0 = OX - H, Y0 = OY - H;
   STile<R> t;
-  s_load<R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  s_load_b<VIN, R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
   if (s_interior(X0, Y0, R, o.nx, o.ny))
     s_down_rows<false, R, NU, H>(o, t, X0, Y0, rc);
   else
@@ -327,10 +363,9 @@ __device__ __forceinline__ void s_up_body(const SOp &o, STile<R> &t, const float
   s_post<BOUND, R, NU>(o, t, X0, Y0);
 }
 
-template <int NU>
+template <int NU, bool VIN>
 __global__ void __launch_bounds__(64 * kSW)
-    k_sup(SOp o, const float *__restrict__ bin, const float *__restrict__ ec,
-          float *__restrict__ xout) {
+    k_sup(SOp o, BIn bin, const float *__restrict__ ec, float *__restrict__ xout) {
   using G = SGeomU<NU>;
   constexpr int H = G::H, TY = G::TY, R = G::R;
   const int wave = threadIdx.x >> 6, lane = s_lane();
@@ -340,7 +375,7 @@ __global__ void __launch_bounds__(64 * kSW)
   const int X0 = OX - H, Y0 = OY - H;
   const int ncx = o.nx / 2, ncy = o.ny / 2;
   STile<R> t;
-  s_load<R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  s_load_b<VIN, R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
   float cr[R / 2 + 3];
   {
     const int I = (X0 >> 1) + lane;
@@ -472,12 +507,18 @@ dim3 s_grid(int nx, int ny) {
 }
 
 template <int NU>
-void sdown_nu(const SOp &o, const float *b, float *rc, hipStream_t st) {
-  k_sdown<NU><<<s_grid<SGeomD<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, rc);
+void sdown_nu(const SOp &o, const BIn &b, float *rc, hipStream_t st) {
+  if (b.v)
+    k_sdown<NU, true><<<s_grid<SGeomD<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, rc);
+  else
+    k_sdown<NU, false><<<s_grid<SGeomD<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, rc);
 }
 template <int NU>
-void sup_nu(const SOp &o, const float *b, const float *ec, float *x, hipStream_t st) {
-  k_sup<NU><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+void sup_nu(const SOp &o, const BIn &b, const float *ec, float *x, hipStream_t st) {
+  if (b.v)
+    k_sup<NU, true><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+  else
+    k_sup<NU, false><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
 }
 
 template <typename T>
@@ -516,7 +557,12 @@ bool wsplit_ok(const OpView<float> &D) {
 
 void sdown(const OpView<float> &D, const float *interior, int nu, const float *b, float *rc,
            hipStream_t st) {
-  IRK_S_NU(sdown_nu, make_sop(D, interior), b, rc, st);
+  IRK_S_NU(sdown_nu, make_sop(D, interior), BIn{b, nullptr, nullptr}, rc, st);
+}
+
+void sdown_v(const OpView<float> &D, const float *interior, int nu, const double *v,
+             const double *vscale, float *rc, hipStream_t st) {
+  IRK_S_NU(sdown_nu, make_sop(D, interior), BIn{nullptr, v, vscale}, rc, st);
 }
 
 template <typename T>
@@ -540,7 +586,12 @@ template void scouple<double>(int, int, const double *, const double *, const do
 
 void sup(const OpView<float> &D, const float *interior, int nu, const float *b, const float *ec,
          float *x, hipStream_t st) {
-  IRK_S_NU(sup_nu, make_sop(D, interior), b, ec, x, st);
+  IRK_S_NU(sup_nu, make_sop(D, interior), BIn{b, nullptr, nullptr}, ec, x, st);
+}
+
+void sup_v(const OpView<float> &D, const float *interior, int nu, const double *v,
+           const double *vscale, const float *ec, float *x, hipStream_t st) {
+  IRK_S_NU(sup_nu, make_sop(D, interior), BIn{nullptr, v, vscale}, ec, x, st);
 }
 
 }  // namespace kern
