@@ -205,7 +205,7 @@ def test_gradient_finite_differences_256(dev):
     J = 0.5 * torch.sum((uT - u_tgt) ** 2)
     J.backward()
     grad = kt.grad.numpy()
-    say("  J = %.6e, adjoint iterations of the last step %d" % (float(J), S.last_stats.iters))
+    say("  J = %.6e, adjoint iterations of the last step %d" % (float(J.detach()), S.last_stats.iters))
     worst, worst_fixed = 0.0, 0.0
     for idx, dg in enumerate(workloads.fd_directions(n + 2, count=16)):
         an = float(np.sum(grad * kn * dg))
