@@ -523,10 +523,20 @@ __global__ void __launch_bounds__(kBlock)
 // acc): n and zs multiples of 4, Z and acc 16-byte aligned.
 template <typename TZ>
 struct Vec4;
+typedef float NtF4 __attribute__((ext_vector_type(4)));
+typedef double NtD2 __attribute__((ext_vector_type(2)));
 template <>
 struct Vec4<float> {
   __device__ static void load(const float *p, double (&v)[4]) {
     const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  }
+  // non-temporal: data read once and not again soon
+  __device__ static void load_nt(const float *p, double (&v)[4]) {
+    const NtF4 q = __builtin_nontemporal_load(reinterpret_cast<const NtF4 *>(p));
     v[0] = q.x;
     v[1] = q.y;
     v[2] = q.z;
@@ -538,6 +548,14 @@ struct Vec4<double> {
   __device__ static void load(const double *p, double (&v)[4]) {
     const double2 q0 = *reinterpret_cast<const double2 *>(p);
     const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = q0.x;
+    v[1] = q0.y;
+    v[2] = q1.x;
+    v[3] = q1.y;
+  }
+  __device__ static void load_nt(const double *p, double (&v)[4]) {
+    const NtD2 q0 = __builtin_nontemporal_load(reinterpret_cast<const NtD2 *>(p));
+    const NtD2 q1 = __builtin_nontemporal_load(reinterpret_cast<const NtD2 *>(p + 2));
     v[0] = q0.x;
     v[1] = q0.y;
     v[2] = q1.x;
@@ -555,7 +573,7 @@ __global__ void __launch_bounds__(kBlock)
   if (!FIRST) Vec4<double>::load(acc + 4 * e, a);
   for (int j = 0; j < k; ++j) {
     double z[4];
-    Vec4<TZ>::load(Z + (size_t)j * zs + 4 * e, z);
+    Vec4<TZ>::load_nt(Z + (size_t)j * zs + 4 * e, z);  // each column read once
     const double yj = y[j];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] += yj * z[q];
