@@ -49,9 +49,9 @@ SPMM_UPDATE_TRAFFIC = {
     "source": os.path.join("paper_2010_11377_amd", "csrc", "kernels.hip"),
     "begin": "// Kronecker SpMM with fused Gram-Schmidt",
     "end": "// Second Gram-Schmidt pass on the new column",
-    "sha256": "dcf5117c4461b805b33fbb3ba955e3c0ad138ac7529f0c938daf91db6945a23d",
-    "fetch_kib": (1.9999 * 69957.3, 1.9999 * 114688.3),  # a + b (j + 1), scaled
-    "write_kib": 229904.1,
+    "sha256": "274e0f62309aa8f3842fe01de0e925bfd94f41cb444f2a596437d3161ab06ef0",
+    "fetch_kib": (1.9999 * -28345.4, 1.9999 * 114688.6),  # a + b (j + 1), scaled
+    "write_kib": 229904.3,
 }
 
 
@@ -70,13 +70,14 @@ def spmm_source_sha():
     return hashlib.sha256(text[i:j].encode("utf-8")).hexdigest()
 
 
-def spmm_update_traffic(iters_per_step):
+def spmm_update_traffic(iters_per_step, restarts):
     """Average measured HBM bytes per spmm_update launch over the timed steps
-    (launch j of a step reads j + 1 basis columns), or None if the kernel
+    (launch j of a step reads one stage block of V_0 and all of V_1..V_j: the
+    steps converge within their first restart cycle), or None if the kernel
     source differs from the one measured."""
     import hashlib
     rec = SPMM_UPDATE_TRAFFIC
-    if spmm_source_sha() != rec["sha256"]:
+    if spmm_source_sha() != rec["sha256"] or restarts:
         return None
     js = [j for it in iters_per_step for j in range(it)]
     if not js:
@@ -150,15 +151,18 @@ def timed_run(S, u0, K, W, torch, profile_class=None):
     if profile_class is not None:
         S.profile_select(profile_class)
     u = u0.clone()
-    iters = []
+    iters, restarts = [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
         u = S.step(u)
         iters.append(S.last_stats.iters)
+        restarts += S.last_stats.restarts
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = S.profile_read() if profile_class is not None else None
+    if prof is not None:
+        prof["restarts"] = restarts
     S.profile_select(None)
     return u, (t1 - t0), iters, prof
 
@@ -450,7 +454,7 @@ def main():
     roof = None
     if prof and prof["launches"] > 0 and prof["ms"] > 0:
         achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
-        traffic = spmm_update_traffic(head["iters"]) if head["dominant"] == "spmm_update" else None
+        traffic = spmm_update_traffic(head["iters"], head["prof"]["restarts"]) if head["dominant"] == "spmm_update" else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": round(traffic) if traffic else None,

@@ -277,12 +277,16 @@ __device__ __forceinline__ void block_sums(double (&v)[NV]) {
 // displacing the stencil's z rows in the caches (measured at 2048^2, seven
 // stages: update 341 -> 299 us, dots 274 -> 239 us with four columns per
 // block reduction).
+//
+// bc0 != 0: the s stage blocks of V_0 are equal (the first restart cycle of
+// a forward stage system starts from 1 (x) f, block system (3.2)), so block 0 is read
+// once and stands for all of them; the arithmetic is unchanged.
 template <typename TZ, int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
     k_spmm_dots(OpView<double> K, OpView<double> M, const TZ *__restrict__ z, Mat8 hA,
                 const double *__restrict__ V,
                 const double *__restrict__ scale, const KrylovState *__restrict__ ks,
-                double *__restrict__ partial) {
+                double *__restrict__ partial, int bc0) {
   constexpr int NV = 4;  // columns per block reduction
   const size_t N = (size_t)K.nx * K.ny;
   const size_t sN = (size_t)S * N;
@@ -300,8 +304,15 @@ __global__ void __launch_bounds__(kBlock)
       acc[u] = 0.0;
       if (live && m <= jj) {
         const double *Vm = V + (size_t)m * sN;
+        if (m == 0 && bc0) {
+          const double v0 = __builtin_nontemporal_load(Vm + p);
 #pragma unroll
-        for (int r = 0; r < S; ++r) acc[u] += __builtin_nontemporal_load(Vm + (size_t)r * N + p) * w[r];
+          for (int r = 0; r < S; ++r) acc[u] += v0 * w[r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < S; ++r)
+            acc[u] += __builtin_nontemporal_load(Vm + (size_t)r * N + p) * w[r];
+        }
         acc[u] *= scale[m];
       }
     }
@@ -327,7 +338,7 @@ __global__ void __launch_bounds__(kBlock)
     k_spmm_update(OpView<double> K, OpView<double> M, const TZ *__restrict__ z, Mat8 hA,
                   const double *__restrict__ V, const double *__restrict__ scale,
                   const double *__restrict__ hcol, const KrylovState *__restrict__ ks,
-                  double *__restrict__ Vall, double *__restrict__ partial) {
+                  double *__restrict__ Vall, double *__restrict__ partial, int bc0) {
   const size_t N = (size_t)K.nx * K.ny;
   const size_t sN = (size_t)S * N;
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -336,7 +347,15 @@ __global__ void __launch_bounds__(kBlock)
   if (p < N) {
     double w[S];
     kron_apply<TZ, S, MASS>(K, M, z + (size_t)jj * sN, hA, p, N, w);
-    for (int m = 0; m <= jj; ++m) {
+    int m = 0;
+    if (bc0) {
+      const double c = hcol[0] * scale[0];
+      const double v0 = __builtin_nontemporal_load(V + p);
+#pragma unroll
+      for (int r = 0; r < S; ++r) w[r] -= c * v0;
+      m = 1;
+    }
+    for (; m <= jj; ++m) {
       const double c = hcol[m] * scale[m];
       const double *Vm = V + (size_t)m * sN;
 #pragma unroll
@@ -819,14 +838,14 @@ void couple(const OpView<T> &K, const double *v, const double *scale_j, const T 
 template <typename TZ>
 void spmm_dots(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
                int s, const double *V, const double *scale, const KrylovState *ks, int jmax,
-               double *partial, hipStream_t st) {
+               double *partial, bool v0_bcast, hipStream_t st) {
   (void)jmax;
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
   const OpView<double> Mv = M ? *M : K;
 #define L_SPMM_DOTS(S_, MS_)                                                          \
   k_spmm_dots<TZ, S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, z, m, V, scale, ks, \
-                                                          partial)
+                                                          partial, v0_bcast ? 1 : 0)
   if (M) {
     IRK_DISPATCH_S(s, L_SPMM_DOTS, true)
   } else {
@@ -838,13 +857,14 @@ void spmm_dots(const OpView<double> &K, const OpView<double> *M, const TZ *z, co
 template <typename TZ>
 void spmm_update(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
                  int s, const double *V, const double *scale, const double *hcol,
-                 const KrylovState *ks, double *vout, double *partial, hipStream_t st) {
+                 const KrylovState *ks, double *vout, double *partial, bool v0_bcast,
+                 hipStream_t st) {
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
   const OpView<double> Mv = M ? *M : K;
 #define L_SPMM_UPD(S_, MS_)                                                              \
   k_spmm_update<TZ, S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, z, m, V, scale, hcol, ks, \
-                                                            vout, partial)
+                                                            vout, partial, v0_bcast ? 1 : 0)
   if (M) {
     IRK_DISPATCH_S(s, L_SPMM_UPD, true)
   } else {
@@ -985,18 +1005,18 @@ template void couple<double>(const OpView<double> &, const double *, const doubl
                              const double *, const double *, int, int, double *, hipStream_t);
 template void spmm_dots<float>(const OpView<double> &, const OpView<double> *, const float *,
                                const double *, int, const double *, const double *,
-                               const KrylovState *, int, double *, hipStream_t);
+                               const KrylovState *, int, double *, bool, hipStream_t);
 template void spmm_dots<double>(const OpView<double> &, const OpView<double> *, const double *,
                                 const double *, int, const double *, const double *,
-                                const KrylovState *, int, double *, hipStream_t);
+                                const KrylovState *, int, double *, bool, hipStream_t);
 template void spmm_update<float>(const OpView<double> &, const OpView<double> *, const float *,
                                  const double *, int, const double *, const double *,
                                  const double *, const KrylovState *, double *, double *,
-                                 hipStream_t);
+                                 bool, hipStream_t);
 template void spmm_update<double>(const OpView<double> &, const OpView<double> *, const double *,
                                   const double *, int, const double *, const double *,
                                   const double *, const KrylovState *, double *, double *,
-                                  hipStream_t);
+                                  bool, hipStream_t);
 template void accumulate_solution<float>(const float *, size_t, const double *, int, size_t,
                                          double *, bool, hipStream_t);
 template void accumulate_solution<double>(const double *, size_t, const double *, int, size_t,

@@ -201,6 +201,17 @@ void s9up2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cl
 template <typename T>
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
              const T *z, const double *C, int s, int i, T *b, hipStream_t st);
+// The same coupling in two parts, so that the first can run before z_last
+// exists: q = scale_j v_i - K (sum_{k != last} C[k] z_k) (last < 0: every
+// term; q rounded to T), then b = q - c K z_last with c = C[last] (c = 0:
+// b = q).  q and b must not overlap.
+template <typename T>
+void scouple_ahead(int nx, int ny, const double *k_interior, const double *v,
+                   const double *scale_j, const T *z, const double *C, int s, int i, int last,
+                   T *q, hipStream_t st);
+template <typename T>
+void scouple_last(int nx, int ny, const double *k_interior, const T *q, const T *z_last, double c,
+                  T *b, hipStream_t st);
 // The same coupling with K stored per node (FP64 arrays, karr[k * N + p],
 // five-point), wfine.hip.
 template <typename T>
@@ -232,17 +243,19 @@ void vtail(const TailDesc<T> &td, int nu, const T *b, T *x, hipStream_t st);
 // Kronecker SpMM with fused classical Gram-Schmidt dots:
 //   w = (I (x) M) z + (hA (x) K) z, z = Z_j (TZ, stage-major); M == nullptr: M = I
 //   partial[m * nblk + blk] = block sum of <V_m, w> * scale_m, m = 0..j
+// v0_bcast: V_0's s stage blocks are equal and only block 0 is read.
 template <typename TZ>
 void spmm_dots(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
                int s, const double *V, const double *scale, const KrylovState *ks, int jmax,
-               double *partial, hipStream_t st);
+               double *partial, bool v0_bcast, hipStream_t st);
 
 // w = (I (x) M) z + (hA (x) K) z recomputed; vout = w - sum_{m<=j} hcol[m] scale_m V_m;
-// partial[blk] = block sum of vout^2.
+// partial[blk] = block sum of vout^2.  v0_bcast as for spmm_dots.
 template <typename TZ>
 void spmm_update(const OpView<double> &K, const OpView<double> *M, const TZ *z, const double *hA,
                  int s, const double *V, const double *scale, const double *hcol,
-                 const KrylovState *ks, double *vout, double *partial, hipStream_t st);
+                 const KrylovState *ks, double *vout, double *partial, bool v0_bcast,
+                 hipStream_t st);
 
 // Second Gram-Schmidt pass: partial dots of vin with V_0..V_j.
 void vec_dots(const double *vin, size_t n, const double *V, const double *scale,

@@ -1062,13 +1062,17 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       pre_next = false;
       const double kb = op_bytes(S, N, S->K64.npt, 8);
       const double zb = (double)sN * sizeof(T), vb = (double)sN * 8.0;
-      ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb);
-      spmm_dots<T>(K, mass(S), Z, sys.hA, s, S->V, S->scale, S->ks, j, S->partial, st);
+      // the first cycle of a forward system starts from 1 (x) f: the SpMM
+      // passes read one stage block of V_0
+      const bool v0b = sys.forward && restarts == 0;
+      const double v0save = v0b ? (double)(sN - N) * 8.0 : 0.0;
+      ProfTok t1 = prof_begin(S, IRK_KC_SPMM_DOTS, zb + vb * (j + 1) + kb - v0save);
+      spmm_dots<T>(K, mass(S), Z, sys.hA, s, S->V, S->scale, S->ks, j, S->partial, v0b, st);
       prof_end(S, t1);
       reduce_cols(S->partial, nblk_pt, S->ks, j, 1, 0, S->h1, st);
-      ProfTok t2 = prof_begin(S, IRK_KC_SPMM_UPDATE, zb + vb * (j + 2) + kb);
+      ProfTok t2 = prof_begin(S, IRK_KC_SPMM_UPDATE, zb + vb * (j + 2) + kb - v0save);
       spmm_update<T>(K, mass(S), Z, sys.hA, s, S->V, S->scale, S->h1, S->ks, S->V, S->pnorm,
-                     st);
+                     v0b, st);
       prof_end(S, t2);
       // second classical Gram-Schmidt pass, skipped on the device when the
       // first one kept most of ||w|| (reorth = 2) or never run (reorth = 0:

@@ -40,6 +40,7 @@ def run(S, u0, steps):
     for _ in range(steps):
         u = S.step(u)
         its.append(S.last_stats.iters)
+        assert S.last_stats.restarts == 0  # the byte counts below assume one cycle
     torch.cuda.synchronize()
     return u, its
 
@@ -53,6 +54,8 @@ def test_profiled_classes(dev, graphs):
     ref, its = run(S, u0, steps)
     sN = s * n * n
     zb, vb = 4.0 * sN, 8.0 * sN  # FP32 preconditioned column, FP64 basis column
+    # the first cycle's V_0 = 1 (x) f: the SpMM passes read one of its s blocks
+    v0save = 8.0 * (sN - n * n)
 
     # Kronecker SpMM + first Gram-Schmidt update: once per iteration, reading z
     # and columns 0..j and writing column j+1 (constant coefficients: no matrix
@@ -62,7 +65,7 @@ def test_profiled_classes(dev, graphs):
     p = S.profile_read()
     assert torch.equal(u, ref) and its2 == its
     assert p["launches"] == sum(its)
-    want = sum(zb + vb * (j + 2) for it in its for j in range(it))
+    want = sum(zb + vb * (j + 2) - v0save for it in its for j in range(it))
     assert p["bytes"] == want
     assert p["ms"] > 0.0
     say("  spmm_update: %d launches, %.3f ms, %.0f bytes" % (p["launches"], p["ms"], p["bytes"]))
@@ -72,7 +75,7 @@ def test_profiled_classes(dev, graphs):
     p = S.profile_read()
     assert torch.equal(u, ref)
     assert p["launches"] == sum(its)
-    assert p["bytes"] == sum(zb + vb * (j + 1) for it in its for j in range(it))
+    assert p["bytes"] == sum(zb + vb * (j + 1) - v0save for it in its for j in range(it))
 
     # the coupling pass runs once per coupled stage and preconditioner
     # application (the first block under P_LD has no coupling terms: its finest
