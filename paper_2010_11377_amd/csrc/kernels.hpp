@@ -201,17 +201,6 @@ void s9up2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cl
 template <typename T>
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
              const T *z, const double *C, int s, int i, T *b, hipStream_t st);
-// The same coupling in two parts, so that the first can run before z_last
-// exists: q = scale_j v_i - K (sum_{k != last} C[k] z_k) (last < 0: every
-// term; q rounded to T), then b = q - c K z_last with c = C[last] (c = 0:
-// b = q).  q and b must not overlap.
-template <typename T>
-void scouple_ahead(int nx, int ny, const double *k_interior, const double *v,
-                   const double *scale_j, const T *z, const double *C, int s, int i, int last,
-                   T *q, hipStream_t st);
-template <typename T>
-void scouple_last(int nx, int ny, const double *k_interior, const T *q, const T *z_last, double c,
-                  T *b, hipStream_t st);
 // The same coupling with K stored per node (FP64 arrays, karr[k * N + p],
 // five-point), wfine.hip.
 template <typename T>
