@@ -209,13 +209,15 @@ void scouple_var(int nx, int ny, const double *karr, const double *v, const doub
 // Finest-level down pass of stage block `stage`: pre-smoothing from x = 0,
 // rc = R (b - D x), and the pre-smoothed x of every node into xpre.  nx, ny
 // even.  Up pass: x = xpre + P ec, then the post-smoothing (wfine.hip).
-// bscale (device, may be null): the right-hand side is *bscale times b.
+// v0 (device, may be null; b is then unused): the right-hand side is
+// *v0scale times the FP64 vector v0, multiplied in FP64 and rounded to T on
+// load (a block without coupling terms).
 template <typename T>
 void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st,
-           const double *bscale = nullptr);
+           const double *v0 = nullptr, const double *v0scale = nullptr);
 template <typename T>
 void fup(const FineOp<T> &F, int stage, int nu, const T *b, const T *xpre, const T *ec, T *x,
-         hipStream_t st, const double *bscale = nullptr);
+         hipStream_t st, const double *v0 = nullptr, const double *v0scale = nullptr);
 // y[j] *= scale[j], j < k (left.hip).
 void scale_by(double *y, const double *scale, int k, hipStream_t st);
 // The FP32 tail with rows in registers (tail2.hip): levels of at most 64 x 64

@@ -706,8 +706,9 @@ void up_pass(const DevOp<T> &D, int nu, const T *b, const T *ec, const T *xpre, 
 // E takes its smoothing with a zero coarse correction (an up pass from the
 // zero vector, or a tail whose coarsest level returns zero).
 // v0 (a block without coupling terms, finest level on the FP32 split passes
-// or the FP64 passes that keep the pre-smoothed x): the finest level's
-// right-hand side is *v0scale * v0 rounded to T, formed by its passes on load.
+// or on the passes that keep the pre-smoothed x: FP64 constant coefficients,
+// or K per node in either precision): the finest level's right-hand side is
+// *v0scale * v0 rounded to T, formed by its passes on load.
 template <typename T>
 void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done,
             const double *v0 = nullptr, const double *v0scale = nullptr) {
@@ -737,18 +738,13 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done,
       continue;
     }
     if (l == 0 && S->fine_mode && !jacobi(S)) {
-      // b and K per node (read) in, the coarse residual and the pre-smoothed x out
+      // b (or v_0 in FP64) and K per node (read) in, the coarse residual and
+      // the pre-smoothed x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
-      ProfTok t = prof_begin(S, IRK_KC_VDOWN_L0, (double)n * es * 2.25 + kb);
-      if constexpr (std::is_same_v<T, double>) {
-        if (v0) {
-          irk::kern::fdown<T>(fine_op<T>(S), i, nu, v0, lev_b<T>(S, 1), lev_p<T>(S, 0), st,
-                              v0scale);
-          prof_end(S, t);
-          continue;
-        }
-      }
-      irk::kern::fdown<T>(fine_op<T>(S), i, nu, b, lev_b<T>(S, 1), lev_p<T>(S, 0), st);
+      ProfTok t = prof_begin(S, IRK_KC_VDOWN_L0,
+                             (double)n * (v0 ? 8.0 + es * 1.25 : es * 2.25) + kb);
+      irk::kern::fdown<T>(fine_op<T>(S), i, nu, b, lev_b<T>(S, 1), lev_p<T>(S, 0), st, v0,
+                          v0scale);
       prof_end(S, t);
       continue;
     }
@@ -826,18 +822,13 @@ void vcycle(irk_solver *S, int i, const T *b, T *x, bool finest_down_done,
       continue;
     }
     if (l == 0 && S->fine_mode && !jacobi(S)) {
-      // b, the pre-smoothed x, K per node and the coarse correction in, x out
+      // b (or v_0 in FP64), the pre-smoothed x, K per node and the coarse
+      // correction in, x out
       const double kb = S->fine_mode == 2 ? (double)n * 5 * es : 0.0;
-      ProfTok t = prof_begin(S, IRK_KC_VUP_L0, (double)n * es * 3.25 + kb);
+      ProfTok t = prof_begin(S, IRK_KC_VUP_L0,
+                             (double)n * (v0 ? 8.0 + es * 2.25 : es * 3.25) + kb);
       const T *ec0 = l == E ? zero : lev_x<T>(S, 1);
-      if constexpr (std::is_same_v<T, double>) {
-        if (v0) {
-          irk::kern::fup<T>(fine_op<T>(S), i, nu, v0, lev_p<T>(S, 0), ec0, x, st, v0scale);
-          prof_end(S, t);
-          continue;
-        }
-      }
-      irk::kern::fup<T>(fine_op<T>(S), i, nu, b, lev_p<T>(S, 0), ec0, x, st);
+      irk::kern::fup<T>(fine_op<T>(S), i, nu, b, lev_p<T>(S, 0), ec0, x, st, v0, v0scale);
       prof_end(S, t);
       continue;
     }
@@ -891,7 +882,11 @@ void apply_precond(irk_solver *S, const double *v, const double *scale_j, T *z, 
     if constexpr (std::is_same_v<T, float>)
       ws9_0 = D0 && !split_ok<T>(*D0) && ws9_usable<T>(*D0, S->opt.nu_pre);
     const bool split64 = std::is_same_v<T, double> && D0 && kcouple_ok(S);
-    if (S->fine_mode == 2) {
+    if (ncoup == 0 && D0 && !jacobi(S) && S->fine_mode == 2) {
+      // no coupling terms: the finest passes (K per node) form scale_j v_i
+      // on load
+      vcycle<T>(S, i, nullptr, z + (size_t)i * N, false, v + (size_t)i * N, scale_j);
+    } else if (S->fine_mode == 2) {
       // K per node: the streaming coupling pass reads K's FP64 arrays
       const double vbytes = (double)N * (8.0 + es * (ncoup + 1)) + (ncoup ? (double)N * 5 * 8 : 0.0);
       ProfTok tk = prof_begin(S, IRK_KC_COUPLE, vbytes);

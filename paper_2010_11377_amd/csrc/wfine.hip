@@ -268,24 +268,30 @@ __device__ __forceinline__ void f_down_tile(const FOp<T> &o, FTile<T, FGeomD<T, 
   }
 }
 
-// bscale (may be null): b is *bscale times the vector bin, scaled on load
-// (the right-hand side of a block without coupling terms in FP64, the same
-// bits the coupling pass would write).
+// The right-hand side of a block without coupling terms, formed on load:
+// rows of *vscale times the FP64 vector v, multiplied in FP64 and rounded to
+// T (the same bits the coupling pass would write).
 template <typename T, int R>
-__device__ __forceinline__ void f_scale_b(const double *bscale, FTile<T, R> &t) {
-  if (!bscale) return;
-  const T sc = (T)*bscale;
+__device__ __forceinline__ void f_load_v(const double *__restrict__ v,
+                                         const double *__restrict__ vscale, T (&a)[R], T (&b)[R],
+                                         int X0, int Y0, int nx, int ny) {
+  const double sc = *vscale;
+  const int gx = X0 + 2 * f_lane();
+  const bool inx = gx >= 0 && gx < nx;  // nx and gx even: gx + 1 < nx too
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    t.ba[r] = sc * t.ba[r];
-    t.bb[r] = sc * t.bb[r];
+    const int gy = Y0 + r;
+    double2 w = make_double2(0.0, 0.0);
+    if (inx && gy >= 0 && gy < ny) w = *reinterpret_cast<const double2 *>(v + (size_t)gy * nx + gx);
+    a[r] = (T)(sc * w.x);
+    b[r] = (T)(sc * w.y);
   }
 }
 
 template <typename T, bool VAR, int NU>
 __global__ void __launch_bounds__(64 * kFW)
-    k_fdown(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ bscale,
-            T *__restrict__ rc, T *__restrict__ xpre) {
+    k_fdown(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ vin,
+            const double *__restrict__ vscale, T *__restrict__ rc, T *__restrict__ xpre) {
   using G = FGeomD<T, NU, VAR>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Tile2 tile = xcd_tile();
@@ -293,8 +299,10 @@ __global__ void __launch_bounds__(64 * kFW)
   if (OY >= o.ny) return;
   const int X0 = OX - G::H, Y0 = OY - G::H;
   FTile<T, G::R> t;
-  f_load<T, G::R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
-  f_scale_b<T, G::R>(bscale, t);
+  if (vin)
+    f_load_v<T, G::R>(vin, vscale, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  else
+    f_load<T, G::R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
   if (X0 >= 0 && Y0 >= 0 && X0 + 128 <= o.nx && Y0 + G::R <= o.ny)
     f_down_tile<T, VAR, false, NU>(o, t, X0, Y0, rc, xpre);
   else
@@ -350,8 +358,9 @@ __device__ __forceinline__ void f_up_tile(const FOp<T> &o, FTile<T, FGeomU<T, NU
 
 template <typename T, bool VAR, int NU>
 __global__ void __launch_bounds__(64 * kFW)
-    k_fup(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ bscale,
-          const T *__restrict__ xpre, const T *__restrict__ ec, T *__restrict__ xout) {
+    k_fup(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ vin,
+          const double *__restrict__ vscale, const T *__restrict__ xpre, const T *__restrict__ ec,
+          T *__restrict__ xout) {
   using G = FGeomU<T, NU, VAR>;
   constexpr int R = G::R;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -362,8 +371,10 @@ __global__ void __launch_bounds__(64 * kFW)
   const int X0 = OX - G::HC, Y0 = OY - G::H;
   const int ncx = o.nx / 2, ncy = o.ny / 2;
   FTile<T, R> t;
-  f_load<T, R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
-  f_scale_b<T, R>(bscale, t);
+  if (vin)
+    f_load_v<T, R>(vin, vscale, t.ba, t.bb, X0, Y0, o.nx, o.ny);
+  else
+    f_load<T, R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
   f_load<T, R>(xpre, t.xa, t.xb, X0, Y0, o.nx, o.ny);
   T cr[R / 2 + 3];
   {
@@ -407,15 +418,16 @@ FOp<T> make_fop(const FineOp<T> &F, int stage) {
 }
 
 template <typename T, bool VAR, int NU>
-void fdown_launch(const FOp<T> &o, const T *b, const double *bs, T *rc, T *xpre, hipStream_t st) {
-  k_fdown<T, VAR, NU><<<f_grid<FGeomD<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, bs, rc,
-                                                                                  xpre);
+void fdown_launch(const FOp<T> &o, const T *b, const double *v0, const double *vs, T *rc, T *xpre,
+                  hipStream_t st) {
+  k_fdown<T, VAR, NU><<<f_grid<FGeomD<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, v0, vs,
+                                                                                  rc, xpre);
 }
 template <typename T, bool VAR, int NU>
-void fup_launch(const FOp<T> &o, const T *b, const double *bs, const T *xpre, const T *ec, T *x,
-                hipStream_t st) {
-  k_fup<T, VAR, NU><<<f_grid<FGeomU<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, bs, xpre,
-                                                                                ec, x);
+void fup_launch(const FOp<T> &o, const T *b, const double *v0, const double *vs, const T *xpre,
+                const T *ec, T *x, hipStream_t st) {
+  k_fup<T, VAR, NU><<<f_grid<FGeomU<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, v0, vs,
+                                                                                xpre, ec, x);
 }
 
 }  // namespace
@@ -424,42 +436,42 @@ namespace kern {
 
 template <typename T>
 void fdown(const FineOp<T> &F, int stage, int nu, const T *b, T *rc, T *xpre, hipStream_t st,
-           const double *bscale) {
+           const double *v0, const double *v0scale) {
   const FOp<T> o = make_fop(F, stage);
   if (F.kq) {
-    if (nu == 1) fdown_launch<T, true, 1>(o, b, bscale, rc, xpre, st);
-    else if (nu == 2) fdown_launch<T, true, 2>(o, b, bscale, rc, xpre, st);
-    else fdown_launch<T, true, 3>(o, b, bscale, rc, xpre, st);
+    if (nu == 1) fdown_launch<T, true, 1>(o, b, v0, v0scale, rc, xpre, st);
+    else if (nu == 2) fdown_launch<T, true, 2>(o, b, v0, v0scale, rc, xpre, st);
+    else fdown_launch<T, true, 3>(o, b, v0, v0scale, rc, xpre, st);
   } else {
-    if (nu == 1) fdown_launch<T, false, 1>(o, b, bscale, rc, xpre, st);
-    else if (nu == 2) fdown_launch<T, false, 2>(o, b, bscale, rc, xpre, st);
-    else fdown_launch<T, false, 3>(o, b, bscale, rc, xpre, st);
+    if (nu == 1) fdown_launch<T, false, 1>(o, b, v0, v0scale, rc, xpre, st);
+    else if (nu == 2) fdown_launch<T, false, 2>(o, b, v0, v0scale, rc, xpre, st);
+    else fdown_launch<T, false, 3>(o, b, v0, v0scale, rc, xpre, st);
   }
 }
 
 template <typename T>
 void fup(const FineOp<T> &F, int stage, int nu, const T *b, const T *xpre, const T *ec, T *x,
-         hipStream_t st, const double *bscale) {
+         hipStream_t st, const double *v0, const double *v0scale) {
   const FOp<T> o = make_fop(F, stage);
   if (F.kq) {
-    if (nu == 1) fup_launch<T, true, 1>(o, b, bscale, xpre, ec, x, st);
-    else if (nu == 2) fup_launch<T, true, 2>(o, b, bscale, xpre, ec, x, st);
-    else fup_launch<T, true, 3>(o, b, bscale, xpre, ec, x, st);
+    if (nu == 1) fup_launch<T, true, 1>(o, b, v0, v0scale, xpre, ec, x, st);
+    else if (nu == 2) fup_launch<T, true, 2>(o, b, v0, v0scale, xpre, ec, x, st);
+    else fup_launch<T, true, 3>(o, b, v0, v0scale, xpre, ec, x, st);
   } else {
-    if (nu == 1) fup_launch<T, false, 1>(o, b, bscale, xpre, ec, x, st);
-    else if (nu == 2) fup_launch<T, false, 2>(o, b, bscale, xpre, ec, x, st);
-    else fup_launch<T, false, 3>(o, b, bscale, xpre, ec, x, st);
+    if (nu == 1) fup_launch<T, false, 1>(o, b, v0, v0scale, xpre, ec, x, st);
+    else if (nu == 2) fup_launch<T, false, 2>(o, b, v0, v0scale, xpre, ec, x, st);
+    else fup_launch<T, false, 3>(o, b, v0, v0scale, xpre, ec, x, st);
   }
 }
 
 template void fdown<float>(const FineOp<float> &, int, int, const float *, float *, float *,
-                           hipStream_t, const double *);
+                           hipStream_t, const double *, const double *);
 template void fup<float>(const FineOp<float> &, int, int, const float *, const float *,
-                         const float *, float *, hipStream_t, const double *);
+                         const float *, float *, hipStream_t, const double *, const double *);
 template void fdown<double>(const FineOp<double> &, int, int, const double *, double *, double *,
-                            hipStream_t, const double *);
+                            hipStream_t, const double *, const double *);
 template void fup<double>(const FineOp<double> &, int, int, const double *, const double *,
-                          const double *, double *, hipStream_t, const double *);
+                          const double *, double *, hipStream_t, const double *, const double *);
 
 }  // namespace kern
 }  // namespace irk
