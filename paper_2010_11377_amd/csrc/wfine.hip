@@ -523,6 +523,14 @@ __global__ void __launch_bounds__(64 * kFW)
   const bool inx = gxa >= 0 && gxa < nx;
   const bool out = lane >= 1 && lane < 63 && inx;
   const double sc = *scale_j;
+  // v's rows first: their loads are in flight while the z rows arrive
+  double2 vr[kVRows];
+#pragma unroll
+  for (int r = 0; r < kVRows; ++r) {
+    const int gy = OY + r;
+    vr[r] = make_double2(0.0, 0.0);
+    if (inx && gy < ny) vr[r] = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * nx + gxa);
+  }
   double ca[kVRows + 2], cb[kVRows + 2];
 #pragma unroll
   for (int r = 0; r < kVRows + 2; ++r) {
@@ -545,8 +553,7 @@ __global__ void __launch_bounds__(64 * kFW)
     const int gy = OY + r;
     if (gy >= ny) break;
     const size_t p = (size_t)gy * nx + gxa;
-    double2 vv = make_double2(0.0, 0.0);
-    if (inx) vv = *reinterpret_cast<const double2 *>(v + (size_t)i * N + p);
+    const double2 vv = vr[r];
     double va = sc * vv.x, vb = sc * vv.y;
     if (NK > 0) {
       double2 ks = make_double2(0.0, 0.0), kw = ks, kcn = ks, ke = ks, kn = ks;

@@ -467,6 +467,15 @@ __global__ void __launch_bounds__(64 * kSW)
   const bool inx = gxa >= 0 && gxa < ko.nx;
   const bool out = lane >= 1 && lane < 63 && inx;
   const double sc = *scale_j;
+  // v's rows first: their loads are in flight while the z rows arrive
+  double2 vr[kCRows];
+#pragma unroll
+  for (int r = 0; r < kCRows; ++r) {
+    const int gy = OY + r;
+    vr[r] = make_double2(0.0, 0.0);
+    if (inx && gy < ko.ny)
+      vr[r] = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * ko.nx + gxa);
+  }
   double ca[kCRows + 2], cb[kCRows + 2];
 #pragma unroll
   for (int r = 0; r < kCRows + 2; ++r) {
@@ -488,8 +497,7 @@ __global__ void __launch_bounds__(64 * kSW)
   for (int r = 0; r < kCRows; ++r) {
     const int gy = OY + r;
     if (gy >= ko.ny) break;
-    double2 vv = make_double2(0.0, 0.0);
-    if (inx) vv = *reinterpret_cast<const double2 *>(v + (size_t)i * N + (size_t)gy * ko.nx + gxa);
+    const double2 vv = vr[r];
     double va = sc * vv.x, vb = sc * vv.y;
     if (NK > 0) {
       va -= ko.c * ca[r + 1] + ko.s * ca[r] + ko.n * ca[r + 2] + ko.w * s_prev_d(cb[r + 1]) +
