@@ -201,7 +201,9 @@ irk_status irk_update_operator(irk_solver *S, const irk_csr *K);
 /* One IRK step (Sec. 2): u_np1 = u_n + h sum_i b_i k_i with k from
  * right-preconditioned flexible GMRES on the stage system.  u_n_dev and
  * u_np1_dev are device arrays of N doubles and may alias.  st may be NULL.
- * IRK_E_NOT_CONVERGED still writes the best iterate. */
+ * IRK_E_NOT_CONVERGED still writes the best iterate; after other errors the
+ * contents of u_np1_dev are unspecified when it does not overlap u_n_dev
+ * (the true-residual check writes its candidate there). */
 irk_status irk_step(irk_solver *S, const double *u_n_dev, double *u_np1_dev, irk_stats *st);
 
 /* Same as irk_step and also writes the stage vectors k (device, s*N doubles,

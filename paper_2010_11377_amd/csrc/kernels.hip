@@ -614,11 +614,14 @@ __global__ void __launch_bounds__(kBlock)
   u_out[p] = a;
 }
 
+// u_out (may be null): also u_out = u_in + sum_i wts_i x_i at every node, in
+// k_combine's order (the new state, should this residual pass the test).
 template <int S, bool MASS>
 __global__ void __launch_bounds__(kBlock)
     k_residual_full(OpView<double> K, OpView<double> M, const double *__restrict__ x, Mat8 hA,
                     const double *__restrict__ rhs, const double *__restrict__ f,
-                    double *__restrict__ V0, double *__restrict__ partial) {
+                    double *__restrict__ V0, double *__restrict__ partial,
+                    const double *__restrict__ u_in, Row8 wts, double *__restrict__ u_out) {
   const size_t N = (size_t)K.nx * K.ny;
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
   double val = 0.0;
@@ -631,6 +634,12 @@ __global__ void __launch_bounds__(kBlock)
       const double res = b - w[r];
       if (V0) V0[(size_t)r * N + p] = res;
       val += res * res;
+    }
+    if (u_out) {
+      double a = u_in[p];
+#pragma unroll
+      for (int i = 0; i < S; ++i) a += wts.c[i] * x[(size_t)i * N + p];
+      u_out[p] = a;
     }
   }
   const double t = block_sum(val);
@@ -938,12 +947,15 @@ void combine_stages(const double *u_in, const double *x, const double *wts, int 
 
 void residual_full(const OpView<double> &K, const OpView<double> *M, const double *x,
                    const double *hA, int s, const double *rhs, const double *f, double *V0,
-                   double *partial, hipStream_t st) {
+                   double *partial, hipStream_t st, const double *u_in, const double *wts,
+                   double *u_out) {
   const size_t N = (size_t)K.nx * K.ny;
   const Mat8 m = pack_mat(hA, s);
   const OpView<double> Mv = M ? *M : K;
-#define L_RES(S_, MS_) \
-  k_residual_full<S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, x, m, rhs, f, V0, partial)
+  const Row8 w = u_out ? pack_row(wts, s) : Row8{};
+#define L_RES(S_, MS_)                                                                  \
+  k_residual_full<S_, MS_><<<nblocks(N), kBlock, 0, st>>>(K, Mv, x, m, rhs, f, V0, partial, \
+                                                          u_in, w, u_out)
   if (M) {
     IRK_DISPATCH_S(s, L_RES, true)
   } else {

@@ -290,10 +290,12 @@ void combine_stages(const double *u_in, const double *x, const double *wts, int 
 
 // r = rhs - (I (x) M + hA (x) K) x; V0 = r (unless V0 == nullptr); partial
 // norms.  rhs == nullptr with f given means rhs = 1 (x) f; M == nullptr means
-// M = I.
+// M = I.  u_out != nullptr: also u_out = u_in + sum_i wts[i] x_i, bit for bit
+// what combine_stages writes (u_out must not overlap u_in or x).
 void residual_full(const OpView<double> &K, const OpView<double> *M, const double *x,
                    const double *hA, int s, const double *rhs, const double *f, double *V0,
-                   double *partial, hipStream_t st);
+                   double *partial, hipStream_t st, const double *u_in = nullptr,
+                   const double *wts = nullptr, double *u_out = nullptr);
 
 // y = (I (x) M + hA (x) K) x for a double stage-major x (the Kronecker SpMM
 // alone); M == nullptr means M = I.

@@ -158,6 +158,7 @@ struct irk_solver {
   hipStream_t cap_stream = nullptr;  // capture only; replays go to `stream`
   long long graph_replays = 0;
   hipEvent_t resid_ev = nullptr;  // recorded after an iteration's residual estimate reaches the host
+  bool u_written = false;  // the last converged true-residual pass wrote the step's output
 
   std::string err;
 };
@@ -996,6 +997,10 @@ struct SystemDesc {
   // right-hand side: forward = 1 (x) (g - K u); otherwise rhs (s*N) given
   const double *u;
   bool forward;
+  // forward steps whose output does not overlap u: the true-residual pass
+  // also writes u + sum_i h b_i k_i here; a converged check then leaves
+  // S->u_written set and the step skips its combining pass
+  double *u_out = nullptr;
 };
 
 template <typename T>
@@ -1142,8 +1147,9 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     // residual vector itself is only stored when a next cycle needs it.
     const double *rhs_full = sys.forward ? nullptr : S->rhs;
     const bool need_v0 = status != IRK_OK;
+    double *u_out = sys.forward ? sys.u_out : nullptr;
     residual_full(K, mass(S), S->acc, sys.hA, s, rhs_full, S->f, need_v0 ? S->V : nullptr,
-                  S->partial, st);
+                  S->partial, st, sys.u, S->hb, u_out);
     finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
     HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1156,10 +1162,12 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     }
     if (beta <= S->opt.rtol * beta0) {
       status = IRK_OK;
+      S->u_written = u_out != nullptr;
       break;
     }
     if (total >= S->opt.max_iter) {
       status = IRK_E_NOT_CONVERGED;
+      S->u_written = u_out != nullptr;  // the best iterate, as the combining pass would write
       break;
     }
     if (!need_v0) {  // the estimate was optimistic: store the residual for the restart
@@ -1666,10 +1674,16 @@ static irk_status step_impl(irk_solver *S, const double *u_n, double *u_np1, dou
   return guarded(S, [&]() -> irk_status {
     const double t0 = now_s();
     SystemDesc sys{S->hA, S->Cfwd, S->ord_fwd, u_n, true};
+    // the true-residual pass may write the output only if it does not
+    // overlap u_n: a restart after a failed check reads u_n again
+    const bool apart = u_np1 + S->N <= u_n || u_n + S->N <= u_np1;
+    sys.u_out = apart ? u_np1 : nullptr;
+    S->u_written = false;
     irk_stats local{};
     irk_status r = run_system(S, sys, st ? st : &local);
     if (r == IRK_OK || r == IRK_E_NOT_CONVERGED) {
-      irk::kern::combine_stages(u_n, S->acc, S->hb, S->s, S->N, u_np1, S->stream);
+      if (!S->u_written)
+        irk::kern::combine_stages(u_n, S->acc, S->hb, S->s, S->N, u_np1, S->stream);
       if (k_out)
         HIP_TRY(hipMemcpyAsync(k_out, S->acc, S->sN * sizeof(double), hipMemcpyDeviceToDevice,
                                S->stream));
