@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -1676,7 +1677,9 @@ static irk_status step_impl(irk_solver *S, const double *u_n, double *u_np1, dou
     SystemDesc sys{S->hA, S->Cfwd, S->ord_fwd, u_n, true};
     // the true-residual pass may write the output only if it does not
     // overlap u_n: a restart after a failed check reads u_n again
-    const bool apart = u_np1 + S->N <= u_n || u_n + S->N <= u_np1;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(u_n), a1 = reinterpret_cast<uintptr_t>(u_np1);
+    const uintptr_t nb = S->N * sizeof(double);
+    const bool apart = a1 + nb <= a0 || a0 + nb <= a1;
     sys.u_out = apart ? u_np1 : nullptr;
     S->u_written = false;
     irk_stats local{};
