@@ -201,6 +201,13 @@ void s9up2(const OpView<T> &Df, const T *cls_f, const OpView<T> &Dc, const T *cl
 template <typename T>
 void scouple(int nx, int ny, const double *k_interior, const double *v, const double *scale_j,
              const T *z, const double *C, int s, int i, T *b, hipStream_t st);
+// The true residual pass of residual_full for a uniform five-point K with
+// even nx and M = I (hA: s x s row-major, host; k_interior as for scouple),
+// in the coupling pass's streaming layout; V0, u_in/wts/u_out as there.
+// Returns the number of block partials written to partial.
+int residual_split(int nx, int ny, const double *k_interior, const double *x, const double *hA,
+                   int s, const double *f, double *V0, double *partial, hipStream_t st,
+                   const double *u_in, const double *wts, double *u_out);
 // The same coupling with K stored per node (FP64 arrays, karr[k * N + p],
 // five-point), wfine.hip.
 template <typename T>

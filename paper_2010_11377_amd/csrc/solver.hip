@@ -1004,6 +1004,20 @@ struct SystemDesc {
   double *u_out = nullptr;
 };
 
+// The true residual 1 (x) f - A k (forward systems) or rhs - A k of the
+// accumulated k into V0 (may be null) with block partials of its squared norm;
+// returns their count.  Uniform five-point K with M = I: the streaming pass.
+int true_residual(irk_solver *S, const SystemDesc &sys, int nblk_pt, double *V0, double *u_out,
+                  hipStream_t st) {
+  if (sys.forward && !mass(S) && kcouple_ok(S))
+    return irk::kern::residual_split(S->nx, S->ny, S->K64.interior, S->acc, sys.hA, S->s, S->f,
+                                     V0, S->partial, st, sys.u, S->hb, u_out);
+  irk::kern::residual_full(S->K64.view(), mass(S), S->acc, sys.hA, S->s,
+                           sys.forward ? nullptr : S->rhs, S->f, V0, S->partial, st, sys.u,
+                           S->hb, u_out);
+  return nblk_pt;
+}
+
 template <typename T>
 irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
   using namespace irk::kern;
@@ -1146,12 +1160,10 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
     // (single-pass Gram-Schmidt can make the estimate optimistic) or starts
     // the next restart cycle.  A converged estimate usually passes, so the
     // residual vector itself is only stored when a next cycle needs it.
-    const double *rhs_full = sys.forward ? nullptr : S->rhs;
     const bool need_v0 = status != IRK_OK;
     double *u_out = sys.forward ? sys.u_out : nullptr;
-    residual_full(K, mass(S), S->acc, sys.hA, s, rhs_full, S->f, need_v0 ? S->V : nullptr,
-                  S->partial, st, sys.u, S->hb, u_out);
-    finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
+    const int nres = true_residual(S, sys, nblk_pt, need_v0 ? S->V : nullptr, u_out, st);
+    finalize_norm(S->partial, nres, S->scale, 0, S->norm_dev, st);
     HIP_TRY(hipMemcpyAsync(S->host_resid, S->norm_dev, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     beta = S->host_resid[0];
@@ -1172,8 +1184,8 @@ irk_status fgmres(irk_solver *S, const SystemDesc &sys, irk_stats *stats) {
       break;
     }
     if (!need_v0) {  // the estimate was optimistic: store the residual for the restart
-      residual_full(K, mass(S), S->acc, sys.hA, s, rhs_full, S->f, S->V, S->partial, st);
-      finalize_norm(S->partial, nblk_pt, S->scale, 0, S->norm_dev, st);
+      const int nr = true_residual(S, sys, nblk_pt, S->V, nullptr, st);
+      finalize_norm(S->partial, nr, S->scale, 0, S->norm_dev, st);
     }
     status = IRK_E_NOT_CONVERGED;
     ++restarts;

@@ -548,9 +548,142 @@ void scouple_launch(const KOpD &ko, const double *v, const double *scale_j, cons
 #undef L_SCOUPLE
 }
 
+// The true residual r = 1 (x) f - (I (x) I + hA (x) K) x of the stage system
+// for a uniform five-point K and M = I, streamed like the coupling pass: two
+// adjacent columns per lane, kRRows output rows per wave, K x_st of every
+// stage from its rows in registers (east/west neighbours by DPP), all in
+// FP64.  Optionally V0 = r and u_out = u_in + sum_i wts_i x_i (summed in
+// stage order from u_in, as the combining pass does).  One block sum of |r|^2
+// per workgroup into partial[block].
+constexpr int kRRows = 2;  // 4 rows: 116 us (256 VGPRs + AGPRs, one wave per SIMD), 2 rows: 93 us
+
+struct RMat {
+  double a[kMaxStages][kMaxStages];  // a[q][st]: hA row q
+  double w[kMaxStages];              // state weights h b_i
+};
+
+__device__ __forceinline__ double s_block_sum(double v) {
+  __shared__ double red[kSW];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kSW; ++q) r += red[q];
+  }
+  return r;
+}
+
+template <int S>
+__global__ void __launch_bounds__(64 * kSW)
+    k_resid_split(KOpD ko, const double *__restrict__ x, RMat m, const double *__restrict__ f,
+                  double *__restrict__ V0, double *__restrict__ partial,
+                  const double *__restrict__ u_in, double *__restrict__ u_out) {
+  const int wave = threadIdx.x >> 6, lane = s_lane();
+  const Tile2 tile = xcd_tile();
+  const int OX = tile.x * kCTXO, OY = (tile.y * kSW + wave) * kRRows;
+  double val = 0.0;
+  if (OY < ko.ny) {
+    const int X0 = OX - 2, gxa = X0 + 2 * lane;
+    const size_t N = (size_t)ko.nx * ko.ny;
+    const bool inx = gxa >= 0 && gxa < ko.nx;
+    const bool out = lane >= 1 && lane < 63 && inx;
+    double wa[S][kRRows], wb[S][kRRows], ua[kRRows], ub[kRRows];
+#pragma unroll
+    for (int r = 0; r < kRRows; ++r) {
+      const int gy = OY + r;
+      double2 u = make_double2(0.0, 0.0);
+      if (u_out && inx && gy < ko.ny)
+        u = *reinterpret_cast<const double2 *>(u_in + (size_t)gy * ko.nx + gxa);
+      ua[r] = u.x;
+      ub[r] = u.y;
+#pragma unroll
+      for (int q = 0; q < S; ++q) wa[q][r] = wb[q][r] = 0.0;
+    }
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const double *xs = x + (size_t)st * N;
+      double ra[kRRows + 2], rb[kRRows + 2];
+#pragma unroll
+      for (int r = 0; r < kRRows + 2; ++r) {
+        const int gy = OY - 1 + r;
+        double2 v = make_double2(0.0, 0.0);
+        if (inx && gy >= 0 && gy < ko.ny)
+          v = *reinterpret_cast<const double2 *>(xs + (size_t)gy * ko.nx + gxa);
+        ra[r] = v.x;
+        rb[r] = v.y;
+      }
+#pragma unroll
+      for (int r = 0; r < kRRows; ++r) {
+        const double ka = ko.c * ra[r + 1] + ko.s * ra[r] + ko.n * ra[r + 2] +
+                          ko.w * s_prev_d(rb[r + 1]) + ko.e * rb[r + 1];
+        const double kb = ko.c * rb[r + 1] + ko.s * rb[r] + ko.n * rb[r + 2] + ko.w * ra[r + 1] +
+                          ko.e * s_next_d(ra[r + 1]);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          wa[q][r] += m.a[q][st] * ka;
+          wb[q][r] += m.a[q][st] * kb;
+        }
+        wa[st][r] += ra[r + 1];
+        wb[st][r] += rb[r + 1];
+        ua[r] += m.w[st] * ra[r + 1];
+        ub[r] += m.w[st] * rb[r + 1];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRRows; ++r) {
+      const int gy = OY + r;
+      if (gy >= ko.ny) break;
+      const size_t p = (size_t)gy * ko.nx + gxa;
+      double2 fv = make_double2(0.0, 0.0);
+      if (inx) fv = *reinterpret_cast<const double2 *>(f + p);
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const double resa = fv.x - wa[q][r], resb = fv.y - wb[q][r];
+        if (out) {
+          val += resa * resa + resb * resb;
+          if (V0) *reinterpret_cast<double2 *>(V0 + (size_t)q * N + p) = make_double2(resa, resb);
+        }
+      }
+      if (u_out && out) *reinterpret_cast<double2 *>(u_out + p) = make_double2(ua[r], ub[r]);
+    }
+  }
+  const double t = s_block_sum(val);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
 }  // namespace
 
 namespace kern {
+
+int residual_split(int nx, int ny, const double *k_interior, const double *x, const double *hA,
+                   int s, const double *f, double *V0, double *partial, hipStream_t st,
+                   const double *u_in, const double *wts, double *u_out) {
+  RMat m{};
+  for (int q = 0; q < s; ++q)
+    for (int k = 0; k < s; ++k) m.a[q][k] = hA[(size_t)q * s + k];
+  if (u_out)
+    for (int k = 0; k < s; ++k) m.w[k] = wts[k];
+  const KOpD ko{nx, ny, k_interior[1], k_interior[3], k_interior[4], k_interior[5], k_interior[7]};
+  const dim3 grid((nx + kCTXO - 1) / kCTXO, (ny + kRRows * kSW - 1) / (kRRows * kSW));
+#define L_RESID(S_)                                                                        \
+  k_resid_split<S_><<<grid, 64 * kSW, 0, st>>>(ko, x, m, f, V0, partial, u_in, u_out)
+  switch (s) {
+    case 1: L_RESID(1); break;
+    case 2: L_RESID(2); break;
+    case 3: L_RESID(3); break;
+    case 4: L_RESID(4); break;
+    case 5: L_RESID(5); break;
+    case 6: L_RESID(6); break;
+    case 7: L_RESID(7); break;
+    default: L_RESID(8); break;
+  }
+#undef L_RESID
+  return (int)(grid.x * grid.y);
+}
 
 bool wsplit_ok(const OpView<float> &D) {
   return D.npt == 5 && D.uniform && D.cls && D.nx % 2 == 0 && D.ny % 2 == 0;
