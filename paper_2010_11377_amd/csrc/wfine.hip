@@ -198,14 +198,14 @@ __host__ __device__ constexpr int f_even(int h) { return (h + 1) & ~1; }
 // coarse column beyond the tile, so their correction is wrong).
 // Tile heights keep the registers of x, b (and, VAR, the coefficients of
 // the rows in flight) within about 200 per lane.  With K per node the FP32
-// tiles are 8 rows high: the grids these passes serve (1024^2) then give
-// every CU workgroups and each wave a shorter row chain (double glazing
-// 1024^2: 5.25 -> 4.82 ms per step against 16-row tiles).
+// tiles are 4 rows high: the grids these passes serve (1024^2) then give
+// every CU workgroups and each wave a short row chain (double glazing
+// 1024^2: 5.25 ms per step with 16-row tiles, 4.83 with 8, 4.72 with 4).
 template <typename T, int NU, bool VAR>
 struct FGeomD {
   static constexpr int K = 2 * NU;
   static constexpr int H = f_even(2 * NU);
-  static constexpr int TY = sizeof(T) == 4 ? (VAR ? 8 : 16) : 8;
+  static constexpr int TY = sizeof(T) == 4 ? (VAR ? 4 : 16) : 8;
   static constexpr int R = TY + 2 * H;
   static constexpr int TXO = 128 - 2 * H;
 };
@@ -214,7 +214,7 @@ struct FGeomU {
   static constexpr int K = 2 * NU;
   static constexpr int H = f_even(2 * NU);
   static constexpr int HC = H + 2;
-  static constexpr int TY = sizeof(T) == 4 ? (VAR ? 8 : 24) : 8;
+  static constexpr int TY = sizeof(T) == 4 ? (VAR ? 4 : 24) : 8;
   static constexpr int R = TY + 2 * H;
   static constexpr int TXO = 128 - 2 * HC;
 };
