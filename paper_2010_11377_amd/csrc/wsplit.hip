@@ -182,17 +182,19 @@ __host__ __device__ constexpr int even_up(int h) { return (h + 1) & ~1; }
 // down tiles: the latency-bound down pass runs best with many short waves
 // (two or three per SIMD hide each other's load latency); the up pass is
 // bound by its arithmetic, where the halo's share of the work decides.
-template <int NU>
+// SMALL: 4-row tiles for grids whose tall tiles would leave CUs without a
+// workgroup (below 256 of them): more, shorter row chains.
+template <int NU, bool SMALL = false>
 struct SGeomD {
   static constexpr int H = even_up(2 * NU);
-  static constexpr int TY = 16;
+  static constexpr int TY = SMALL ? 4 : 16;
   static constexpr int R = TY + 2 * H;
   static constexpr int TXO = 128 - 2 * H;
 };
-template <int NU>
+template <int NU, bool SMALL = false>
 struct SGeomU {
   static constexpr int H = even_up(4 * NU - 1);
-  static constexpr int TY = NU == 1 ? 32 : (NU == 2 ? 24 : 16);
+  static constexpr int TY = SMALL ? 4 : (NU == 1 ? 32 : (NU == 2 ? 24 : 16));
   static constexpr int R = TY + 2 * H;
   static constexpr int TXO = 128 - 2 * H;
 };
@@ -245,10 +247,10 @@ __device__ __forceinline__ void s_down_rows(const SOp &o, STile<R> &t, int X0, i
   }
 }
 
-template <int NU, bool VIN>
+template <int NU, bool VIN, bool SMALL>
 __global__ void __launch_bounds__(64 * kSW)
     k_sdown(SOp o, BIn bin, float *__restrict__ rc) {
-  using G = SGeomD<NU>;
+  using G = SGeomD<NU, SMALL>;
   constexpr int H = G::H, TY = G::TY, R = G::R;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // Y0 uniform
   const Tile2 tile = xcd_tile();
@@ -363,10 +365,10 @@ __device__ __forceinline__ void s_up_body(const SOp &o, STile<R> &t, const float
   s_post<BOUND, R, NU>(o, t, X0, Y0);
 }
 
-template <int NU, bool VIN>
+template <int NU, bool VIN, bool SMALL>
 __global__ void __launch_bounds__(64 * kSW)
     k_sup(SOp o, BIn bin, const float *__restrict__ ec, float *__restrict__ xout) {
-  using G = SGeomU<NU>;
+  using G = SGeomU<NU, SMALL>;
   constexpr int H = G::H, TY = G::TY, R = G::R;
   const int wave = threadIdx.x >> 6, lane = s_lane();
   const Tile2 tile = xcd_tile();
@@ -514,19 +516,41 @@ dim3 s_grid(int nx, int ny) {
   return dim3((nx + G::TXO - 1) / G::TXO, (ny + G::TY * kSW - 1) / (G::TY * kSW));
 }
 
+template <typename G>
+bool s_fills(int nx, int ny) {
+  const dim3 g = s_grid<G>(nx, ny);
+  return g.x * g.y >= 256;
+}
+
+template <int NU, bool SMALL>
+void sdown_geo(const SOp &o, const BIn &b, float *rc, hipStream_t st) {
+  const dim3 g = s_grid<SGeomD<NU, SMALL>>(o.nx, o.ny);
+  if (b.v)
+    k_sdown<NU, true, SMALL><<<g, 64 * kSW, 0, st>>>(o, b, rc);
+  else
+    k_sdown<NU, false, SMALL><<<g, 64 * kSW, 0, st>>>(o, b, rc);
+}
 template <int NU>
 void sdown_nu(const SOp &o, const BIn &b, float *rc, hipStream_t st) {
-  if (b.v)
-    k_sdown<NU, true><<<s_grid<SGeomD<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, rc);
+  if (s_fills<SGeomD<NU>>(o.nx, o.ny))
+    sdown_geo<NU, false>(o, b, rc, st);
   else
-    k_sdown<NU, false><<<s_grid<SGeomD<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, rc);
+    sdown_geo<NU, true>(o, b, rc, st);
+}
+template <int NU, bool SMALL>
+void sup_geo(const SOp &o, const BIn &b, const float *ec, float *x, hipStream_t st) {
+  const dim3 g = s_grid<SGeomU<NU, SMALL>>(o.nx, o.ny);
+  if (b.v)
+    k_sup<NU, true, SMALL><<<g, 64 * kSW, 0, st>>>(o, b, ec, x);
+  else
+    k_sup<NU, false, SMALL><<<g, 64 * kSW, 0, st>>>(o, b, ec, x);
 }
 template <int NU>
 void sup_nu(const SOp &o, const BIn &b, const float *ec, float *x, hipStream_t st) {
-  if (b.v)
-    k_sup<NU, true><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+  if (s_fills<SGeomU<NU>>(o.nx, o.ny))
+    sup_geo<NU, false>(o, b, ec, x, st);
   else
-    k_sup<NU, false><<<s_grid<SGeomU<NU>>(o.nx, o.ny), 64 * kSW, 0, st>>>(o, b, ec, x);
+    sup_geo<NU, true>(o, b, ec, x, st);
 }
 
 template <typename T>
