@@ -201,30 +201,32 @@ __host__ __device__ constexpr int f_even(int h) { return (h + 1) & ~1; }
 // tiles are 4 rows high: the grids these passes serve (1024^2) then give
 // every CU workgroups and each wave a short row chain (double glazing
 // 1024^2: 5.25 ms per step with 16-row tiles, 4.83 with 8, 4.72 with 4).
-template <typename T, int NU, bool VAR>
+// SMALL: 4-row tiles, taken when the usual ones would leave CUs without a
+// workgroup (fewer than 256).
+template <typename T, int NU, bool VAR, bool SMALL = false>
 struct FGeomD {
   static constexpr int K = 2 * NU;
   static constexpr int H = f_even(2 * NU);
-  static constexpr int TY = sizeof(T) == 4 ? (VAR ? 4 : 16) : 8;
+  static constexpr int TY = SMALL ? 4 : (sizeof(T) == 4 ? (VAR ? 4 : 16) : 8);
   static constexpr int R = TY + 2 * H;
   static constexpr int TXO = 128 - 2 * H;
 };
-template <typename T, int NU, bool VAR>
+template <typename T, int NU, bool VAR, bool SMALL = false>
 struct FGeomU {
   static constexpr int K = 2 * NU;
   static constexpr int H = f_even(2 * NU);
   static constexpr int HC = H + 2;
-  static constexpr int TY = sizeof(T) == 4 ? (VAR ? 4 : 24) : 8;
+  static constexpr int TY = SMALL ? 4 : (sizeof(T) == 4 ? (VAR ? 4 : 24) : 8);
   static constexpr int R = TY + 2 * H;
   static constexpr int TXO = 128 - 2 * HC;
 };
 
 // Down pass of one tile.  BOUND: the tile reaches past the grid.
-template <typename T, bool VAR, bool BOUND, int NU>
-__device__ __forceinline__ void f_down_tile(const FOp<T> &o, FTile<T, FGeomD<T, NU, VAR>::R> &t,
-                                            int X0, int Y0, T *__restrict__ rc,
-                                            T *__restrict__ xpre) {
-  using G = FGeomD<T, NU, VAR>;
+template <typename T, bool VAR, bool BOUND, int NU, bool SMALL>
+__device__ __forceinline__ void f_down_tile(const FOp<T> &o,
+                                            FTile<T, FGeomD<T, NU, VAR, SMALL>::R> &t, int X0,
+                                            int Y0, T *__restrict__ rc, T *__restrict__ xpre) {
+  using G = FGeomD<T, NU, VAR, SMALL>;
   constexpr int K = G::K, H = G::H, R = G::R;
   const int lane = f_lane();
   const int gxa = X0 + 2 * lane;
@@ -291,11 +293,11 @@ __device__ __forceinline__ void f_load_v(const double *__restrict__ v,
   }
 }
 
-template <typename T, bool VAR, int NU>
+template <typename T, bool VAR, int NU, bool SMALL>
 __global__ void __launch_bounds__(64 * kFW)
     k_fdown(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ vin,
             const double *__restrict__ vscale, T *__restrict__ rc, T *__restrict__ xpre) {
-  using G = FGeomD<T, NU, VAR>;
+  using G = FGeomD<T, NU, VAR, SMALL>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Tile2 tile = xcd_tile();
   const int OX = tile.x * G::TXO, OY = (tile.y * kFW + wave) * G::TY;
@@ -307,20 +309,21 @@ __global__ void __launch_bounds__(64 * kFW)
   else
     f_load<T, G::R>(bin, t.ba, t.bb, X0, Y0, o.nx, o.ny);
   if (X0 >= 0 && Y0 >= 0 && X0 + 128 <= o.nx && Y0 + G::R <= o.ny)
-    f_down_tile<T, VAR, false, NU>(o, t, X0, Y0, rc, xpre);
+    f_down_tile<T, VAR, false, NU, SMALL>(o, t, X0, Y0, rc, xpre);
   else
-    f_down_tile<T, VAR, true, NU>(o, t, X0, Y0, rc, xpre);
+    f_down_tile<T, VAR, true, NU, SMALL>(o, t, X0, Y0, rc, xpre);
 }
 
 // Up pass of one tile: stage 0 adds the prolongated correction to row r,
 // stages 1..K relax in colours 1, 0, 1, ...; row r is written once stage K
 // has passed it.  cr[q]: coarse correction of this lane's coarse column in
 // coarse row Y0/2 - 1 + q.
-template <typename T, bool VAR, bool BOUND, int NU>
-__device__ __forceinline__ void f_up_tile(const FOp<T> &o, FTile<T, FGeomU<T, NU, VAR>::R> &t,
-                                          const T (&cr)[FGeomU<T, NU, VAR>::R / 2 + 3], int X0,
-                                          int Y0, T *__restrict__ xout) {
-  using G = FGeomU<T, NU, VAR>;
+template <typename T, bool VAR, bool BOUND, int NU, bool SMALL>
+__device__ __forceinline__ void f_up_tile(const FOp<T> &o,
+                                          FTile<T, FGeomU<T, NU, VAR, SMALL>::R> &t,
+                                          const T (&cr)[FGeomU<T, NU, VAR, SMALL>::R / 2 + 3],
+                                          int X0, int Y0, T *__restrict__ xout) {
+  using G = FGeomU<T, NU, VAR, SMALL>;
   constexpr int K = G::K, H = G::H, R = G::R, HC = G::HC;
   const int lane = f_lane();
   const int gxa = X0 + 2 * lane;
@@ -359,12 +362,12 @@ __device__ __forceinline__ void f_up_tile(const FOp<T> &o, FTile<T, FGeomU<T, NU
   }
 }
 
-template <typename T, bool VAR, int NU>
+template <typename T, bool VAR, int NU, bool SMALL>
 __global__ void __launch_bounds__(64 * kFW)
     k_fup(FOp<T> o, const T *__restrict__ bin, const double *__restrict__ vin,
           const double *__restrict__ vscale, const T *__restrict__ xpre, const T *__restrict__ ec,
           T *__restrict__ xout) {
-  using G = FGeomU<T, NU, VAR>;
+  using G = FGeomU<T, NU, VAR, SMALL>;
   constexpr int R = G::R;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = f_lane();
@@ -389,9 +392,9 @@ __global__ void __launch_bounds__(64 * kFW)
     }
   }
   if (X0 >= 0 && Y0 >= 0 && X0 + 128 <= o.nx && Y0 + R <= o.ny)
-    f_up_tile<T, VAR, false, NU>(o, t, cr, X0, Y0, xout);
+    f_up_tile<T, VAR, false, NU, SMALL>(o, t, cr, X0, Y0, xout);
   else
-    f_up_tile<T, VAR, true, NU>(o, t, cr, X0, Y0, xout);
+    f_up_tile<T, VAR, true, NU, SMALL>(o, t, cr, X0, Y0, xout);
 }
 
 template <typename G>
@@ -420,17 +423,31 @@ FOp<T> make_fop(const FineOp<T> &F, int stage) {
   return o;
 }
 
+template <typename G>
+bool f_fills(int nx, int ny) {
+  const dim3 g = f_grid<G>(nx, ny);
+  return g.x * g.y >= 256;
+}
+
 template <typename T, bool VAR, int NU>
 void fdown_launch(const FOp<T> &o, const T *b, const double *v0, const double *vs, T *rc, T *xpre,
                   hipStream_t st) {
-  k_fdown<T, VAR, NU><<<f_grid<FGeomD<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, v0, vs,
-                                                                                  rc, xpre);
+  if (f_fills<FGeomD<T, NU, VAR>>(o.nx, o.ny))
+    k_fdown<T, VAR, NU, false><<<f_grid<FGeomD<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(
+        o, b, v0, vs, rc, xpre);
+  else
+    k_fdown<T, VAR, NU, true><<<f_grid<FGeomD<T, NU, VAR, true>>(o.nx, o.ny), 64 * kFW, 0, st>>>(
+        o, b, v0, vs, rc, xpre);
 }
 template <typename T, bool VAR, int NU>
 void fup_launch(const FOp<T> &o, const T *b, const double *v0, const double *vs, const T *xpre,
                 const T *ec, T *x, hipStream_t st) {
-  k_fup<T, VAR, NU><<<f_grid<FGeomU<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(o, b, v0, vs,
-                                                                                xpre, ec, x);
+  if (f_fills<FGeomU<T, NU, VAR>>(o.nx, o.ny))
+    k_fup<T, VAR, NU, false><<<f_grid<FGeomU<T, NU, VAR>>(o.nx, o.ny), 64 * kFW, 0, st>>>(
+        o, b, v0, vs, xpre, ec, x);
+  else
+    k_fup<T, VAR, NU, true><<<f_grid<FGeomU<T, NU, VAR, true>>(o.nx, o.ny), 64 * kFW, 0, st>>>(
+        o, b, v0, vs, xpre, ec, x);
 }
 
 }  // namespace
